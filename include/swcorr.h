@@ -1,0 +1,209 @@
+/*
+ * swcorr: sliding-window inter-channel Pearson correlation on AMD Instinct
+ * MI355X (gfx950).  C ABI of libswcorr.so.
+ *
+ * The operation (Poyda & Zhizhin, arXiv 1807.06507):
+ *   Two arrays x, y of the same shape and type (Section 3: "both sets must be
+ *   the same size") are walked synchronously by a window of a given size
+ *   with a given step (Introduction, problem statement).  For each window
+ *   position the Pearson coefficient of the window's values is produced
+ *   (Introduction, classical formula), computed here by the paper's method
+ *   (Section 1): separable sliding sums of x, y, xy, x^2 and y^2, one pass per
+ *   dimension (steps 1-3 and the n-dimensional remark), then the per-position
+ *   one-pass formula c = (n Sxy - Sx Sy) / sqrt((n Sxx - Sx^2)(n Syy - Sy^2))
+ *   (Section 1 formula, step 4).
+ *
+ * Output conventions (Section 3, I/O paragraph):
+ *   - FILL: output has the input's size; the value of a window goes to its
+ *     middle cell; windows crossing the border give `invalid_value` (-2).
+ *   - any value <= missing_le (-999) inside a window gives `invalid_value`.
+ *   - a window whose x (or y) values are all equal has a zero denominator
+ *     (Section 3, accuracy paragraph) and gives `invalid_value`.
+ *   Readings where the paper is silent (see the design notes): CLIP uses the
+ *   in-bounds part of a border window (n = in-bounds count); VALID visits
+ *   only windows that fit and compacts the output; for even k the window has
+ *   floor(k/2) cells before its centre and k-1-floor(k/2) after; with step s,
+ *   output j is centred at j*s (FILL, CLIP) or starts at j*s (VALID); NaN
+ *   and +-Inf count as missing; integer inputs never have missing values.
+ *
+ * Arrays are C-ordered (shape[ndim-1] is contiguous).  All data pointers are
+ * DEVICE pointers on the current HIP device.  `stream` is a hipStream_t
+ * (NULL = the legacy default stream), passed as void* so that this header
+ * does not depend on HIP headers.
+ *
+ * Error behaviour: every entry point validates its arguments first and
+ * returns an error code without touching any memory or launching anything
+ * when they are invalid.  Nothing here aborts, throws or prints (unless the
+ * environment variable SWC_LOG=1 asks for host-side debug output).
+ */
+#ifndef SWCORR_H
+#define SWCORR_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define SWC_VERSION_MAJOR 0
+#define SWC_VERSION_MINOR 1
+
+typedef enum swc_status {
+    SWC_OK = 0,
+    SWC_ERR_NULL = 1,        /* a required pointer is NULL */
+    SWC_ERR_NDIM = 2,        /* ndim not in {1,2,3} */
+    SWC_ERR_SHAPE = 3,       /* shape < 1, or VALID with shape < window */
+    SWC_ERR_WINDOW = 4,      /* window < 1, or above the supported limits */
+    SWC_ERR_STEP = 5,        /* step < 1 */
+    SWC_ERR_DTYPE = 6,       /* unknown element type */
+    SWC_ERR_BORDER = 7,      /* unknown border policy */
+    SWC_ERR_ACCUM = 8,       /* unknown accumulation mode, or not valid for the dtype */
+    SWC_ERR_WORKSPACE = 9,   /* a caller-provided buffer is too small */
+    SWC_ERR_LAUNCH = 10,     /* the kernel launch failed */
+    SWC_ERR_DEVICE = 11,     /* no usable device, or a sticky device error */
+    SWC_ERR_UNSUPPORTED = 12,/* valid request outside what this build implements */
+    SWC_ERR_PARAM = 13       /* invalid launch parameters */
+} swc_status;
+
+typedef enum swc_dtype { SWC_U8 = 0, SWC_U16 = 1, SWC_F32 = 2 } swc_dtype;
+
+typedef enum swc_border {
+    SWC_BORDER_FILL = 0,   /* same-size output, border windows -> invalid (paper) */
+    SWC_BORDER_CLIP = 1,   /* same-size output, border windows clipped */
+    SWC_BORDER_VALID = 2   /* only windows that fit; output shrinks */
+} swc_border;
+
+typedef enum swc_accum {
+    /* u8/u16: exact integer sums, correctly rounded float32 output.
+     * f32: FP64 sliding sums of exact FP64 products, FP64 epilogue, windows
+     * that a rigorous error bound cannot certify are recomputed by the
+     * two-pass formula (flags always exact). */
+    SWC_ACC_DEFAULT = 0,
+    /* f32 only: plain FP32 sums and FP32 epilogue (comparator, no
+     * certification; flags may differ). */
+    SWC_ACC_NAIVE_F32 = 1,
+    /* f32 only: compensated (TwoSum) FP32 sliding sums, FP64 epilogue. */
+    SWC_ACC_COMP_F32 = 2
+} swc_accum;
+
+/* Per-output flag bits (optional uint8 map, same shape as c). */
+#define SWC_FLAG_BORDER 1u
+#define SWC_FLAG_MISSING 2u
+#define SWC_FLAG_ZVAR_X 4u
+#define SWC_FLAG_ZVAR_Y 8u
+
+/* Problem descriptor.  Entries of shape/window/step beyond ndim are ignored.
+ * window[d] = k_d and step[d] = s_d per dimension, in the same (C) order as
+ * shape.  invalid_value is written wherever a flag is set (paper: -2).
+ * missing_le: float32 values <= this are missing (paper: -999); -INFINITY
+ * keeps only NaN/Inf as missing.  Layout is fixed (80 bytes). */
+typedef struct swc_problem {
+    int32_t ndim;
+    int32_t dtype;        /* swc_dtype */
+    int32_t border;       /* swc_border */
+    int32_t accum;        /* swc_accum */
+    int64_t shape[3];
+    int32_t window[3];
+    int32_t step[3];
+    float invalid_value;
+    int32_t reserved0;    /* must be 0 */
+    double missing_le;
+} swc_problem;
+
+/* Launch parameters (tile shape); all-zero means "use the tuned default".
+ *   cols_per_lane: contiguous-axis elements owned by one lane (1, 2, 4, 8)
+ *   tile_rows:     output rows (2-D) / planes (3-D) / 64*cols_per_lane-sample
+ *                  rows (1-D) marched by one wave before it restarts
+ *   waves_per_block: 1, 2, 4 or 8 wavefronts per workgroup
+ *   min_waves_per_eu: occupancy hint of the kernel variant (0, 1, 2, 4)  */
+typedef struct swc_launch_params {
+    int32_t cols_per_lane;
+    int32_t tile_rows;
+    int32_t waves_per_block;
+    int32_t min_waves_per_eu;
+    int32_t reserved[4];
+} swc_launch_params;
+
+/* ---- host-only queries (never touch the device) ------------------------ */
+
+/* Check a descriptor.  Returns SWC_OK or the first error found. */
+swc_status swc_validate(const swc_problem *p);
+
+/* Output shape for a valid descriptor: out[d] for d < ndim (FILL/CLIP:
+ * ceil(N/s); VALID: floor((N-k)/s)+1); entries >= ndim are set to 1. */
+swc_status swc_output_shape(const swc_problem *p, int64_t out[3]);
+
+/* Static, NUL-terminated description of a status code (never NULL). */
+const char *swc_status_str(swc_status s);
+
+/* Library version as major*100 + minor. */
+int32_t swc_version(void);
+
+/* ---- single problem ---------------------------------------------------- */
+
+/* Correlation map of one pair (Section 1 steps 1-4, fused into one kernel).
+ *   x, y:  device arrays of p->shape, element type p->dtype (read only)
+ *   c:     device float32 array of swc_output_shape(p) (written)
+ *   flags: device uint8 array of the same shape, or NULL (written if given)
+ *   stream: hipStream_t; the call is asynchronous on it, allocates nothing
+ *   and does not synchronize.
+ * x/y must not alias c/flags.  The caller owns all buffers and keeps them
+ * alive until the stream work completes. */
+swc_status swc_corr(const swc_problem *p, const void *x, const void *y, float *c,
+                    uint8_t *flags, void *stream);
+
+/* Same as swc_corr with explicit launch parameters (NULL = tuned default).
+ * Used by the autotuner; returns SWC_ERR_PARAM for unsupported values. */
+swc_status swc_corr_ex(const swc_problem *p, const swc_launch_params *lp, const void *x,
+                       const void *y, float *c, uint8_t *flags, void *stream);
+
+/* ---- tuning table ------------------------------------------------------ */
+
+/* Register launch parameters for problems like `p` (same dtype, ndim,
+ * accumulation mode and window-size bucket).  Host only.  Thread-safe. */
+swc_status swc_tune_set(const swc_problem *p, const swc_launch_params *lp);
+
+/* Parameters swc_corr would use for `p` (tuned entry or built-in default). */
+swc_status swc_tune_get(const swc_problem *p, swc_launch_params *lp);
+
+/* ---- batches of independent pairs (one persistent launch) -------------- */
+
+typedef struct swc_batch_plan swc_batch_plan;
+
+/* Build a plan for n pairs (problems may differ in shape, window, step and
+ * border, but must share dtype and accumulation mode, and be 2-D).  The
+ * arrays x[i], y[i], c[i], flags[i] (flags may be NULL, or contain NULLs)
+ * are device pointers kept by the plan.  Allocates and fills the plan's
+ * device-side work list (synchronous, not capture-safe).  The plan owns that
+ * memory; free it with swc_batch_plan_destroy. */
+swc_status swc_batch_plan_create(int32_t n, const swc_problem *p, const void *const *x,
+                                 const void *const *y, float *const *c,
+                                 uint8_t *const *flags, const swc_launch_params *lp,
+                                 swc_batch_plan **out);
+
+/* One persistent launch computing every pair of the plan on `stream`.
+ * Asynchronous, allocates nothing, safe to capture into a hipGraph. */
+swc_status swc_batch_launch(const swc_batch_plan *plan, void *stream);
+
+/* Number of work items (tiles) in the plan, for reporting. */
+int64_t swc_batch_plan_items(const swc_batch_plan *plan);
+
+/* Free the plan (NULL is ignored).  The caller ensures no launch of it is
+ * still in flight. */
+void swc_batch_plan_destroy(swc_batch_plan *plan);
+
+/* ---- debug switches ---------------------------------------------------- */
+
+/* Bit 0: send every integer-input output through the exact big-integer
+ * rounding decision and every float-input output through the two-pass
+ * window recomputation (results must not change).  Host only; applies to
+ * launches issued after the call.  Also set from SWC_FORCE_EXACT_FALLBACK=1
+ * at library load. */
+void swc_set_debug(int32_t bits);
+int32_t swc_get_debug(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SWCORR_H */

@@ -1,0 +1,353 @@
+"""Sliding-window inter-channel Pearson correlation on MI355X (gfx950).
+
+Thin ctypes binding of ``libswcorr.so`` (C ABI in ``include/swcorr.h``):
+argument marshalling only.  Every step of the computation runs in the HIP
+kernels of the library; torch supplies device memory and streams.  There is
+no CPU fallback: if the library is missing the import of the binding fails.
+
+    import torch, paper_1807_06507_amd as swc
+    c = swc.corr(x, y, window=7)                     # FILL, step 1 (paper)
+    c, flags = swc.corr(x, y, (7, 7), border="clip", return_flags=True)
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import threading
+
+__all__ = [
+    "Problem", "LaunchParams", "corr", "corr_into", "output_shape", "validate", "status_str",
+    "tune_set", "tune_get", "set_debug", "get_debug", "BatchPlan", "library_path",
+    "SwcError", "FLAG_BORDER", "FLAG_MISSING", "FLAG_ZVAR_X", "FLAG_ZVAR_Y",
+]
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "libswcorr.so")
+
+U8, U16, F32 = 0, 1, 2
+BORDERS = {"fill": 0, "clip": 1, "valid": 2}
+ACCUMS = {"default": 0, "naive": 1, "naive_f32": 1, "comp": 2, "comp_f32": 2}
+FLAG_BORDER, FLAG_MISSING, FLAG_ZVAR_X, FLAG_ZVAR_Y = 1, 2, 4, 8
+
+STATUS = {
+    0: "SWC_OK", 1: "SWC_ERR_NULL", 2: "SWC_ERR_NDIM", 3: "SWC_ERR_SHAPE", 4: "SWC_ERR_WINDOW",
+    5: "SWC_ERR_STEP", 6: "SWC_ERR_DTYPE", 7: "SWC_ERR_BORDER", 8: "SWC_ERR_ACCUM",
+    9: "SWC_ERR_WORKSPACE", 10: "SWC_ERR_LAUNCH", 11: "SWC_ERR_DEVICE",
+    12: "SWC_ERR_UNSUPPORTED", 13: "SWC_ERR_PARAM",
+}
+
+
+class SwcError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{STATUS.get(code, code)}: {msg}")
+        self.code = code
+
+
+class Problem(ctypes.Structure):
+    _fields_ = [
+        ("ndim", ctypes.c_int32), ("dtype", ctypes.c_int32), ("border", ctypes.c_int32),
+        ("accum", ctypes.c_int32), ("shape", ctypes.c_int64 * 3), ("window", ctypes.c_int32 * 3),
+        ("step", ctypes.c_int32 * 3), ("invalid_value", ctypes.c_float),
+        ("reserved0", ctypes.c_int32), ("missing_le", ctypes.c_double),
+    ]
+
+
+class LaunchParams(ctypes.Structure):
+    _fields_ = [
+        ("cols_per_lane", ctypes.c_int32), ("tile_rows", ctypes.c_int32),
+        ("waves_per_block", ctypes.c_int32), ("min_waves_per_eu", ctypes.c_int32),
+        ("reserved", ctypes.c_int32 * 4),
+    ]
+
+    def as_tuple(self):
+        return (self.cols_per_lane, self.tile_rows, self.waves_per_block, self.min_waves_per_eu)
+
+
+assert ctypes.sizeof(Problem) == 80
+assert ctypes.sizeof(LaunchParams) == 32
+
+_lock = threading.Lock()
+_lib = None
+
+
+def library_path() -> str:
+    return _LIB_PATH
+
+
+def _load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    with _lock:
+        if _lib is not None:
+            return _lib
+        if not os.path.exists(_LIB_PATH):
+            raise ImportError(
+                f"{_LIB_PATH} is missing: build it with `python -m paper_1807_06507_amd.build` "
+                "(there is no CPU fallback)")
+        lib = ctypes.CDLL(_LIB_PATH)
+        P = ctypes.POINTER(Problem)
+        LP = ctypes.POINTER(LaunchParams)
+        vp = ctypes.c_void_p
+        lib.swc_validate.argtypes = [P]
+        lib.swc_output_shape.argtypes = [P, ctypes.POINTER(ctypes.c_int64)]
+        lib.swc_status_str.argtypes = [ctypes.c_int]
+        lib.swc_status_str.restype = ctypes.c_char_p
+        lib.swc_version.restype = ctypes.c_int32
+        lib.swc_corr.argtypes = [P, vp, vp, vp, vp, vp]
+        lib.swc_corr_ex.argtypes = [P, LP, vp, vp, vp, vp, vp]
+        lib.swc_tune_set.argtypes = [P, LP]
+        lib.swc_tune_get.argtypes = [P, LP]
+        lib.swc_set_debug.argtypes = [ctypes.c_int32]
+        lib.swc_get_debug.restype = ctypes.c_int32
+        lib.swc_batch_plan_create.argtypes = [ctypes.c_int32, P, ctypes.POINTER(vp),
+                                              ctypes.POINTER(vp), ctypes.POINTER(vp),
+                                              ctypes.POINTER(vp), LP, ctypes.POINTER(vp)]
+        lib.swc_batch_launch.argtypes = [vp, vp]
+        lib.swc_batch_plan_items.argtypes = [vp]
+        lib.swc_batch_plan_items.restype = ctypes.c_int64
+        lib.swc_batch_plan_destroy.argtypes = [vp]
+        lib.swc_batch_plan_destroy.restype = None
+        for fn in ("swc_validate", "swc_output_shape", "swc_corr", "swc_corr_ex", "swc_tune_set",
+                   "swc_tune_get", "swc_batch_plan_create", "swc_batch_launch"):
+            getattr(lib, fn).restype = ctypes.c_int
+        _lib = lib
+        return lib
+
+
+def status_str(code: int) -> str:
+    return _load().swc_status_str(int(code)).decode()
+
+
+def _check(code):
+    if code != 0:
+        raise SwcError(code, status_str(code))
+
+
+def _per_dim(v, ndim, name):
+    if isinstance(v, int):
+        return [int(v)] * ndim
+    v = [int(t) for t in v]
+    if len(v) != ndim:
+        raise ValueError(f"{name} needs {ndim} entries, got {len(v)}")
+    return v
+
+
+_DT = {"uint8": U8, "u8": U8, "uint16": U16, "u16": U16, "float32": F32, "f32": F32}
+
+
+def _dtype_code(dt) -> int:
+    name = str(dt).replace("torch.", "").replace("numpy.", "")
+    if name not in _DT:
+        raise ValueError(f"unsupported dtype {dt} (uint8, uint16 or float32)")
+    return _DT[name]
+
+
+def make_problem(shape, dtype, window, step=1, border="fill", accum="default",
+                 invalid=-2.0, missing_le=-999.0) -> Problem:
+    ndim = len(shape)
+    if ndim not in (1, 2, 3):
+        raise ValueError("ndim must be 1, 2 or 3")
+    p = Problem()
+    p.ndim = ndim
+    p.dtype = _dtype_code(dtype) if not isinstance(dtype, int) else dtype
+    if border not in BORDERS:
+        raise ValueError(f"border must be one of {sorted(BORDERS)}")
+    p.border = BORDERS[border]
+    if accum not in ACCUMS:
+        raise ValueError(f"accum must be one of {sorted(ACCUMS)}")
+    p.accum = ACCUMS[accum]
+    w = _per_dim(window, ndim, "window")
+    s = _per_dim(step, ndim, "step")
+    for d in range(3):
+        p.shape[d] = int(shape[d]) if d < ndim else 1
+        p.window[d] = w[d] if d < ndim else 1
+        p.step[d] = s[d] if d < ndim else 1
+    p.invalid_value = float(invalid)
+    p.reserved0 = 0
+    p.missing_le = float(missing_le)
+    return p
+
+
+def validate(p: Problem) -> int:
+    return int(_load().swc_validate(ctypes.byref(p)))
+
+
+def output_shape(p: Problem):
+    out = (ctypes.c_int64 * 3)()
+    _check(_load().swc_output_shape(ctypes.byref(p), out))
+    return tuple(int(out[d]) for d in range(p.ndim))
+
+
+def _params(params):
+    if params is None:
+        return None
+    if isinstance(params, LaunchParams):
+        return params
+    lp = LaunchParams()
+    lp.cols_per_lane, lp.tile_rows, lp.waves_per_block = (int(v) for v in params[:3])
+    lp.min_waves_per_eu = int(params[3]) if len(params) > 3 else 0
+    return lp
+
+
+def _stream_handle(stream, device):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream(device)
+    return ctypes.c_void_p(int(stream.cuda_stream))
+
+
+def _check_tensor(t, name):
+    import torch
+    if not isinstance(t, torch.Tensor):
+        raise ValueError(f"{name} must be a torch tensor")
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be on the GPU")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+
+
+def corr_into(p: Problem, x, y, out, flags=None, params=None, stream=None):
+    """Launch on preallocated device tensors (no allocation, asynchronous)."""
+    _check_tensor(x, "x")
+    _check_tensor(y, "y")
+    _check_tensor(out, "out")
+    if flags is not None:
+        _check_tensor(flags, "flags")
+    h = _stream_handle(stream, x.device)
+    lp = _params(params)
+    lib = _load()
+    fptr = ctypes.c_void_p(flags.data_ptr()) if flags is not None else None
+    code = lib.swc_corr_ex(ctypes.byref(p), ctypes.byref(lp) if lp is not None else None,
+                           ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(y.data_ptr()),
+                           ctypes.c_void_p(out.data_ptr()), fptr, h)
+    _check(code)
+    return out
+
+
+def corr(x, y, window, step=1, border="fill", invalid=-2.0, missing_le=-999.0,
+         return_flags=False, accum="default", out=None, flags_out=None, params=None,
+         stream=None):
+    """Sliding-window correlation map of two equal-shape device tensors
+    (uint8, uint16 or float32; 1-D, 2-D or 3-D).  Returns a float32 tensor
+    (and a uint8 flag tensor when ``return_flags``)."""
+    import torch
+    _check_tensor(x, "x")
+    _check_tensor(y, "y")
+    if x.shape != y.shape or x.dtype != y.dtype:
+        raise ValueError("x and y must have the same shape and dtype")
+    if x.device != y.device:
+        raise ValueError("x and y must be on the same device")
+    p = make_problem(tuple(x.shape), x.dtype, window, step, border, accum, invalid, missing_le)
+    code = validate(p)
+    if code != 0:
+        raise ValueError(f"{STATUS.get(code)}: {status_str(code)}")
+    oshape = output_shape(p)
+    if out is None:
+        out = torch.empty(oshape, dtype=torch.float32, device=x.device)
+    elif tuple(out.shape) != oshape or out.dtype != torch.float32:
+        raise ValueError(f"out must be float32 of shape {oshape}")
+    fl = None
+    if return_flags or flags_out is not None:
+        fl = flags_out if flags_out is not None else torch.empty(oshape, dtype=torch.uint8,
+                                                                 device=x.device)
+        if tuple(fl.shape) != oshape or fl.dtype != torch.uint8:
+            raise ValueError(f"flags must be uint8 of shape {oshape}")
+    corr_into(p, x, y, out, fl, params, stream)
+    return (out, fl) if return_flags else out
+
+
+def tune_set(p: Problem, params) -> None:
+    _check(_load().swc_tune_set(ctypes.byref(p), ctypes.byref(_params(params))))
+
+
+def tune_get(p: Problem):
+    lp = LaunchParams()
+    _check(_load().swc_tune_get(ctypes.byref(p), ctypes.byref(lp)))
+    return lp.as_tuple()
+
+
+def set_debug(bits: int) -> None:
+    _load().swc_set_debug(int(bits))
+
+
+def get_debug() -> int:
+    return int(_load().swc_get_debug())
+
+
+class BatchPlan:
+    """Many independent 2-D pairs computed by one persistent launch.
+
+    ``pairs`` is a list of dicts with keys x, y (device tensors), window,
+    and optional step, border, out, flags.  Shares dtype and accum."""
+
+    def __init__(self, pairs, accum="default", invalid=-2.0, missing_le=-999.0, params=None,
+                 return_flags=False):
+        import torch
+        if not pairs:
+            raise ValueError("empty batch")
+        lib = _load()
+        n = len(pairs)
+        probs = (Problem * n)()
+        xs = (ctypes.c_void_p * n)()
+        ys = (ctypes.c_void_p * n)()
+        cs = (ctypes.c_void_p * n)()
+        fs = (ctypes.c_void_p * n)()
+        self.outputs, self.flags = [], []
+        self._keep = []
+        for i, pr in enumerate(pairs):
+            x, y = pr["x"], pr["y"]
+            _check_tensor(x, "x")
+            _check_tensor(y, "y")
+            if x.shape != y.shape or x.dtype != y.dtype:
+                raise ValueError(f"pair {i}: x and y differ in shape/dtype")
+            probs[i] = make_problem(tuple(x.shape), x.dtype, pr["window"], pr.get("step", 1),
+                                    pr.get("border", "clip"), accum, invalid, missing_le)
+            osh = output_shape(probs[i])
+            out = pr.get("out")
+            if out is None:
+                out = torch.empty(osh, dtype=torch.float32, device=x.device)
+            fl = pr.get("flags")
+            if fl is None and return_flags:
+                fl = torch.empty(osh, dtype=torch.uint8, device=x.device)
+            self.outputs.append(out)
+            self.flags.append(fl)
+            self._keep += [x, y]
+            xs[i], ys[i], cs[i] = x.data_ptr(), y.data_ptr(), out.data_ptr()
+            fs[i] = fl.data_ptr() if fl is not None else None
+        lp = _params(params)
+        handle = ctypes.c_void_p()
+        _check(lib.swc_batch_plan_create(n, probs, xs, ys, cs, fs,
+                                         ctypes.byref(lp) if lp is not None else None,
+                                         ctypes.byref(handle)))
+        self._h = handle
+        self._lib = lib
+        self.device = pairs[0]["x"].device
+
+    @property
+    def items(self) -> int:
+        return int(self._lib.swc_batch_plan_items(self._h))
+
+    def launch(self, stream=None):
+        _check(self._lib.swc_batch_launch(self._h, _stream_handle(stream, self.device)))
+        return self.outputs
+
+    def capture_graph(self, stream=None):
+        """Capture one launch into a torch CUDA graph; returns the graph."""
+        import torch
+        g = torch.cuda.CUDAGraph()
+        s = stream or torch.cuda.Stream(device=self.device)
+        with torch.cuda.graph(g, stream=s):
+            self.launch(stream=torch.cuda.current_stream(self.device))
+        return g
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.swc_batch_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,49 @@
+// Host-side interfaces between the C ABI (swc_api.cpp) and the kernel
+// translation units.  Internal to libswcorr.so.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "swcorr.h"
+
+namespace swc {
+
+// Resolved launch configuration.
+struct LaunchCfg {
+    int R;       // contiguous-axis elements per lane
+    int TH;      // rows (2-D) / planes (3-D) / sample rows (1-D) per tile
+    int wpb;     // waves per workgroup
+    int minw;    // occupancy hint variant (0 = none)
+};
+
+// Kernel mode from (dtype, accum); -1 when the pair is invalid.
+int mode_of(int32_t dtype, int32_t accum);
+
+// Largest float f with f <= t (so that float v <= t  <=>  v <= f).
+float missing_threshold(double t);
+
+// Rounding-error factor for the float certification test (see the design
+// notes): rho * u * n * (3 C Nt + 6 n), with C the longest add/subtract chain
+// a window sum goes through and Nt the bound on terms in any partial sum.
+double cert_factor(int mode, double n, double chain, double nterms);
+
+// Per-dimension window offset: -floor(k/2) for FILL/CLIP, 0 for VALID.
+inline int window_offset(int border, int k) { return border == SWC_BORDER_VALID ? 0 : -(k / 2); }
+
+hipError_t launch_corr1d(const swc_problem& p, const int64_t* oshape, const LaunchCfg& L,
+                         const void* x, const void* y, float* c, uint8_t* flags,
+                         hipStream_t s, int force);
+hipError_t launch_corr2d(const swc_problem& p, const int64_t* oshape, const LaunchCfg& L,
+                         const void* x, const void* y, float* c, uint8_t* flags,
+                         hipStream_t s, int force);
+hipError_t launch_corr3d(const swc_problem& p, const int64_t* oshape, const LaunchCfg& L,
+                         const void* x, const void* y, float* c, uint8_t* flags,
+                         hipStream_t s, int force);
+
+// Whether a configuration is launchable for the problem (host check).
+bool cfg_ok_2d(const swc_problem& p, const LaunchCfg& L);
+bool cfg_ok_1d(const swc_problem& p, const LaunchCfg& L);
+bool cfg_ok_3d(const swc_problem& p, const LaunchCfg& L);
+
+}  // namespace swc

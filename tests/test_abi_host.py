@@ -1,0 +1,158 @@
+"""Host-only checks of the C ABI (no GPU, no device calls).
+
+* libswcorr.so loads and exports every function declared in include/swcorr.h;
+* swc_validate returns the documented error for every kind of bad input;
+* swc_output_shape follows the stated rule (cross-checked with the oracle's
+  independent implementation of the same rule);
+* the problem-struct layout matches the header (80 bytes).
+"""
+import ctypes
+import os
+import re
+import subprocess
+
+import numpy as np
+import pytest
+
+import oracle
+import paper_1807_06507_amd as swc
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "swcorr.h")
+
+
+def _declared_functions():
+    txt = open(HEADER).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(swc_[a-z0-9_]+)\s*\(", txt)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(swc.library_path()):
+        from paper_1807_06507_amd import build
+        build.build()
+    return swc._load()
+
+
+def test_header_declares_the_boundary():
+    fns = _declared_functions()
+    for f in ("swc_validate", "swc_output_shape", "swc_status_str", "swc_corr", "swc_corr_ex",
+              "swc_batch_plan_create", "swc_batch_launch", "swc_batch_plan_destroy"):
+        assert f in fns
+
+
+def test_every_declared_symbol_is_exported(lib):
+    out = subprocess.run(["nm", "-D", "--defined-only", swc.library_path()],
+                         capture_output=True, text=True, check=True).stdout
+    exported = set(re.findall(r"\bT (swc_[a-z0-9_]+)", out))
+    missing = [f for f in _declared_functions() if f not in exported]
+    assert not missing, missing
+    for f in _declared_functions():
+        assert hasattr(lib, f)
+
+
+def test_struct_layout():
+    assert ctypes.sizeof(swc.Problem) == 80
+    assert swc.Problem.missing_le.offset == 72
+    assert swc.Problem.shape.offset == 16
+    assert ctypes.sizeof(swc.LaunchParams) == 32
+
+
+def _p(**kw):
+    base = dict(shape=(100, 120), dtype="float32", window=(7, 7), step=1, border="fill")
+    base.update(kw)
+    return swc.make_problem(base["shape"], base["dtype"], base["window"], base["step"],
+                            base["border"])
+
+
+def test_validate_ok(lib):
+    assert swc.validate(_p()) == 0
+    assert swc.validate(_p(shape=(5,), window=(3,))) == 0
+    assert swc.validate(_p(shape=(4, 5, 6), window=(3, 3, 3))) == 0
+
+
+def test_validate_errors(lib):
+    p = _p()
+    p.ndim = 0
+    assert swc.validate(p) == 2
+    p = _p()
+    p.ndim = 4
+    assert swc.validate(p) == 2
+    p = _p()
+    p.shape[0] = 0
+    assert swc.validate(p) == 3
+    p = _p(border="valid", shape=(5, 100), window=(7, 7))
+    assert swc.validate(p) == 3
+    p = _p()
+    p.window[1] = 0
+    assert swc.validate(p) == 4
+    p = _p()
+    p.step[0] = 0
+    assert swc.validate(p) == 5
+    p = _p()
+    p.dtype = 7
+    assert swc.validate(p) == 6
+    p = _p()
+    p.border = 3
+    assert swc.validate(p) == 7
+    p = _p(dtype="uint16")
+    p.accum = 1          # naive FP32 is only for float input
+    assert swc.validate(p) == 8
+    p = _p()
+    p.accum = 9
+    assert swc.validate(p) == 8
+    p = _p(dtype="uint16", window=(39, 39))   # 1521 > 1448 cells: exactness limit
+    assert swc.validate(p) == 4
+    p = _p(dtype="uint16", window=(38, 38))
+    assert swc.validate(p) == 0
+    p = _p()
+    p.reserved0 = 1
+    assert swc.validate(p) == 12
+    assert lib.swc_validate(None) == 1
+
+
+def test_null_pointers_rejected_before_launch(lib):
+    p = _p()
+    assert lib.swc_corr(ctypes.byref(p), None, None, None, None, None) == 1
+    assert lib.swc_output_shape(ctypes.byref(p), None) == 1
+    bad = _p()
+    bad.step[0] = -1
+    # validation errors win over null pointers and nothing is launched
+    assert lib.swc_corr(ctypes.byref(bad), None, None, None, None, None) == 5
+
+
+def test_output_shape_matches_oracle_rule(lib):
+    rng = np.random.default_rng(0)
+    for _ in range(300):
+        nd = int(rng.integers(1, 4))
+        shape = tuple(int(v) for v in rng.integers(1, 40, nd))
+        window = tuple(int(v) for v in rng.integers(1, 9, nd))
+        step = tuple(int(v) for v in rng.integers(1, 5, nd))
+        border = ["fill", "clip", "valid"][int(rng.integers(0, 3))]
+        if border == "valid" and any(s < k for s, k in zip(shape, window)):
+            continue
+        p = swc.make_problem(shape, "float32", window, step, border)
+        assert swc.output_shape(p) == oracle.output_shape(shape, window, step, border)
+
+
+def test_status_strings(lib):
+    for code in range(0, 14):
+        s = swc.status_str(code)
+        assert isinstance(s, str) and s
+    assert swc.status_str(999) == "unknown status"
+
+
+def test_tune_roundtrip(lib):
+    p = _p(dtype="uint16", window=(7, 7))
+    swc.tune_set(p, (4, 24, 2))
+    assert swc.tune_get(p)[:3] == (4, 24, 2)
+    with pytest.raises(swc.SwcError):
+        swc.tune_set(p, (3, 24, 2))     # cols_per_lane must be 1, 2, 4 or 8
+
+
+def test_debug_switch(lib):
+    old = swc.get_debug()
+    swc.set_debug(1)
+    assert swc.get_debug() == 1
+    swc.set_debug(old)
