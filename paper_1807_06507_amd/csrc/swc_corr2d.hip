@@ -16,6 +16,7 @@
 //     read from HBM once (halo re-reads hit L2) and c is written once.
 // Tiles are numbered column-major so vertically adjacent tiles, which share
 // k_h - 1 halo rows, run close in time on the same XCD.
+#include "swc_corr2d_fast.hpp"
 #include "swc_device.hpp"
 #include "swc_internal.h"
 
@@ -189,7 +190,7 @@ __global__ void __launch_bounds__(256) corr2d_kernel(P2D g)
                 float cv = 0.f;
                 if (!fl) {
                     WinBox wb{W, 1, rl, rh, cl, ch, 0, 0};
-                    fl = epilogue<M>(S, n, Mx, My, g.cert_g, g.force != 0, g.x, g.y, wb, &cv);
+                    fl = epilogue<M>(S, n, Mx, My, g.cert_g, (g.force & 1) != 0, g.x, g.y, wb, &cv);
                 }
                 if (fl) cv = g.invalid;
                 const int64_t oi = p * g.OW + q;
@@ -300,6 +301,40 @@ hipError_t launch_corr2d(const swc_problem& p, const int64_t* oshape, const Laun
     const double nterms = (double)(g.kh + 1) * (g.kw + 1);
     g.cert_g = cert_factor(mode, (double)g.kh * g.kw, chain, nterms);
     const int grid = (int)((nt + L.wpb - 1) / L.wpb);
+    // register-resident kernel for compiled window widths (debug bit 2 forces
+    // the generic LDS kernel)
+    const bool dims32 = g.H < ((int64_t)1 << 31) - 2 * kWave * 8 && g.W < ((int64_t)1 << 31) - 2 * kWave * 8;
+    if (!(force & 2) && dims32 && fast2d_supported(mode, L.R, g.kw) &&
+        (int64_t)L.wpb * fast2d_lds_per_wave(mode, L.R, g.kh) <= 64 * 1024) {
+        P2DF f;
+        f.x = x;
+        f.y = y;
+        f.c = c;
+        f.flags = flags;
+        f.H = (int)g.H;
+        f.W = (int)g.W;
+        f.OH = (int)g.OH;
+        f.OW = (int)g.OW;
+        f.kh = g.kh;
+        f.sh = g.sh;
+        f.sw = g.sw;
+        f.oh = g.oh;
+        f.ow = g.ow;
+        f.border = g.border;
+        f.invalid = g.invalid;
+        f.miss_thr = g.miss_thr;
+        f.force = force;
+        f.cert_g = g.cert_g;
+        f.TH = g.TH;
+        f.Wq = g.Wq;
+        f.tiles_y = g.tiles_y;
+        f.n_tiles = g.n_tiles;
+        const bool vec = g.vec != 0;
+        const size_t smem = (size_t)L.wpb * fast2d_lds_per_wave(mode, L.R, g.kh);
+        if (mode == MODE_U8) return launch_fast2d_modeu8(f, L.R, g.kw, vec, grid, L.wpb, smem, s);
+        if (mode == MODE_U16) return launch_fast2d_modeu16(f, L.R, g.kw, vec, grid, L.wpb, smem, s);
+        return launch_fast2d_modef64(f, L.R, g.kw, vec, grid, L.wpb, smem, s);
+    }
     switch (mode) {
     case MODE_U8: return launch_m<MODE_U8>(g, L.R, L.wpb, grid, s);
     case MODE_U16: return launch_m<MODE_U16>(g, L.R, L.wpb, grid, s);

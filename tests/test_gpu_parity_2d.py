@@ -143,3 +143,28 @@ def test_parity_config_paper_shaped_full():
     every output, bit-exact."""
     x, y = paper_shaped_u16((3000, 4000), seed=2)
     compare(x, y, (7, 7), 1, "fill", tag="c1-full")
+
+
+@pytest.mark.parametrize("dtype", ["u8", "u16", "f32"])
+def test_register_and_lds_kernels_agree(dtype):
+    """The register-resident kernel (compiled window widths) and the generic
+    LDS kernel give identical integer results and flags, and both match the
+    oracle."""
+    import paper_1807_06507_amd as swc
+    from gpu_util import gpu_corr
+    for shape, window, step, border, params in [
+            ((300, 1000), (7, 7), 1, "fill", (4, 32, 4)),
+            ((211, 777), (3, 9), (1, 2), "clip", (4, 16, 2)),
+            ((97, 1290), (5, 15), 1, "valid", (8, 24, 1)),
+            ((64, 64), (9, 5), (3, 1), "clip", (4, 7, 4))]:
+        x, y = random_pair(shape, dtype, seed=41)
+        a, fa = gpu_corr(x, y, window, step, border, params=params)
+        swc.set_debug(2)
+        try:
+            b, fb = gpu_corr(x, y, window, step, border, params=params)
+        finally:
+            swc.set_debug(0)
+        assert np.array_equal(fa, fb)
+        if dtype != "f32":
+            assert np.array_equal(a.view(np.uint32), b.view(np.uint32))
+        compare(x, y, window, step, border, params=params, tag="fast-kernel")
