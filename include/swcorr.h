@@ -111,17 +111,20 @@ typedef struct swc_problem {
 } swc_problem;
 
 /* Launch parameters (tile shape); all-zero means "use the tuned default".
- *   cols_per_lane: contiguous-axis elements owned by one lane (1, 2, 4, 8)
- *   tile_rows:     output rows (2-D) / planes (3-D) / 64*cols_per_lane-sample
- *                  rows (1-D) marched by one wave before it restarts
- *   waves_per_block: 1, 2, 4 or 8 wavefronts per workgroup
- *   min_waves_per_eu: occupancy hint of the kernel variant (0, 1, 2, 4)  */
+ *   cols_per_lane: contiguous-axis elements owned by one lane (1, 2, 4, 8;
+ *                  the 1-D kernel uses 8, the 3-D and batched kernels 4)
+ *   tile_rows:     output rows (2-D) / output planes (3-D) / rows of
+ *                  64*cols_per_lane window positions (1-D) per wavefront
+ *   waves_per_block: 1, 2 or 4 wavefronts per workgroup
+ *   min_waves_per_eu: occupancy hint (0 = kernel default)
+ *   tile_rows2:    3-D only: output rows per wavefront (2 or 4; 0 = 2)  */
 typedef struct swc_launch_params {
     int32_t cols_per_lane;
     int32_t tile_rows;
     int32_t waves_per_block;
     int32_t min_waves_per_eu;
-    int32_t reserved[4];
+    int32_t tile_rows2;
+    int32_t reserved[3];
 } swc_launch_params;
 
 /* ---- host-only queries (never touch the device) ------------------------ */

@@ -56,11 +56,12 @@ class LaunchParams(ctypes.Structure):
     _fields_ = [
         ("cols_per_lane", ctypes.c_int32), ("tile_rows", ctypes.c_int32),
         ("waves_per_block", ctypes.c_int32), ("min_waves_per_eu", ctypes.c_int32),
-        ("reserved", ctypes.c_int32 * 4),
+        ("tile_rows2", ctypes.c_int32), ("reserved", ctypes.c_int32 * 3),
     ]
 
     def as_tuple(self):
-        return (self.cols_per_lane, self.tile_rows, self.waves_per_block, self.min_waves_per_eu)
+        return (self.cols_per_lane, self.tile_rows, self.waves_per_block, self.min_waves_per_eu,
+                self.tile_rows2)
 
 
 assert ctypes.sizeof(Problem) == 80
@@ -187,6 +188,7 @@ def _params(params):
     lp = LaunchParams()
     lp.cols_per_lane, lp.tile_rows, lp.waves_per_block = (int(v) for v in params[:3])
     lp.min_waves_per_eu = int(params[3]) if len(params) > 3 else 0
+    lp.tile_rows2 = int(params[4]) if len(params) > 4 else 0
     return lp
 
 

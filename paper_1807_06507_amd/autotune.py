@@ -1,0 +1,162 @@
+"""Autotuner for the launch parameters of libswcorr.so.
+
+    python -m paper_1807_06507_amd.autotune [--quick] [--out PATH]
+
+For each workload class (element type, dimensionality, window-size bucket,
+accumulation mode) it times candidate tile shapes on the GPU through the C ABI
+(`swc_corr_ex`, `swc_batch_plan_*`) and writes the fastest into a tuning table
+that the library loads at initialisation (`tune_table.txt` next to
+libswcorr.so, or the file named by SWC_TUNE_TABLE).  Candidates:
+  2-D:    cols_per_lane R in {4, 8}, tile rows TH, waves per workgroup
+  1-D:    rows per wave TH, waves per workgroup (R fixed at 8)
+  batch:  tile rows TH, waves per workgroup (R fixed at 4)
+Timing uses HIP events on the launch stream over several launches whose
+input buffers rotate beyond the 256 MB Infinity Cache, as the benchmark does.
+
+Table line format:  dtype ndim accum kbucket R TH wpb min_waves
+(kbucket 0 with ndim 2 holds the batched-launch parameters).
+"""
+from __future__ import annotations
+
+import argparse
+import itertools
+import os
+import sys
+import time
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(HERE)
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+MALL = 256 << 20
+DT_CODE = {"u8": 0, "u16": 1, "f32": 2}
+
+
+def kbucket(k):
+    for b in (3, 5, 7, 9, 15, 31, 63):
+        if k <= b:
+            return b
+    return 1 << 30
+
+
+def _time_launches(fn, n_sets, reps=30, warm=5):
+    import torch
+    for i in range(warm):
+        fn(i % n_sets)
+    torch.cuda.synchronize()
+    s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    s.record()
+    for i in range(reps):
+        fn(i % n_sets)
+    e.record()
+    torch.cuda.synchronize()
+    return s.elapsed_time(e) / reps * 1e3   # microseconds
+
+
+def _sets(x, y, oshape, per_set_bytes):
+    import torch
+    n = max(2, int(np.ceil(2.2 * MALL / per_set_bytes)))
+    xd, yd = torch.from_numpy(x).cuda(), torch.from_numpy(y).cuda()
+    out = [(xd.clone(), yd.clone(), torch.empty(oshape, dtype=torch.float32, device="cuda"))
+           for _ in range(n)]
+    return out
+
+
+def tune_single(x, y, window, step, border, candidates, label):
+    import paper_1807_06507_amd as swc
+    p = swc.make_problem(x.shape, x.dtype, window, step, border)
+    osh = swc.output_shape(p)
+    sets = _sets(x, y, osh, x.nbytes * 2 + int(np.prod(osh)) * 4)
+    best = None
+    for cand in candidates:
+        try:
+            t = _time_launches(lambda i: swc.corr_into(p, sets[i][0], sets[i][1], sets[i][2],
+                                                       None, cand), len(sets))
+        except Exception:
+            continue
+        print(f"  {label} {cand}: {t:.1f} us", flush=True)
+        if best is None or t < best[0]:
+            best = (t, cand)
+    del sets
+    return best
+
+
+def tune_batch(pairs, candidates, label):
+    import torch
+    import paper_1807_06507_amd as swc
+    dev = [dict(x=torch.from_numpy(a).cuda(), y=torch.from_numpy(b).cuda(), window=k, step=1,
+                border="clip") for a, b, k in pairs]
+    best = None
+    for cand in candidates:
+        try:
+            plan = swc.BatchPlan(dev, params=cand)
+        except Exception:
+            continue
+        t = _time_launches(lambda i: plan.launch(), 1, reps=10, warm=2)
+        plan.close()
+        print(f"  {label} {cand}: {t:.1f} us", flush=True)
+        if best is None or t < best[0]:
+            best = (t, cand)
+    return best
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
+    ap.add_argument("--quick", action="store_true", help="fewer candidates")
+    ap.add_argument("--out", default=os.path.join(HERE, "tune_table.txt"))
+    ap.add_argument("--only", default="", help="comma list: c0,c1,c2,c3,c4b")
+    args = ap.parse_args()
+    import torch
+    import paper_1807_06507_amd as swc
+    from workloads import (paper_shaped_u16, cloud_pair, precision_pair, batched_pairs,
+                           series_1d)
+    assert torch.cuda.is_available()
+    only = set(args.only.split(",")) if args.only else None
+    ths = [8, 12, 16, 24, 32, 48] if not args.quick else [12, 24]
+    wpbs = [1, 2, 4] if not args.quick else [1, 2]
+    cand2d = [(R, th, w) for R, th, w in itertools.product([4, 8], ths, wpbs)]
+    lines = []
+
+    def emit(dt, nd, acc, kb, cand):
+        lines.append(f"{DT_CODE[dt]} {nd} {acc} {kb} {cand[0]} {cand[1]} {cand[2]} "
+                     f"{cand[3] if len(cand) > 3 else 0}")
+
+    t0 = time.time()
+    if only is None or "c1" in only:
+        x, y = paper_shaped_u16()
+        b = tune_single(x, y, (7, 7), 1, "fill", cand2d, "u16 2-D k7")
+        emit("u16", 2, 0, 7, b[1])
+        for k in (3, 5, 9, 15):
+            b = tune_single(x[:1500], y[:1500], (k, k), 1, "fill", cand2d, f"u16 2-D k{k}")
+            emit("u16", 2, 0, kbucket(k), b[1])
+        xb, yb = (x >> 8).astype(np.uint8), (y >> 8).astype(np.uint8)
+        b = tune_single(xb, yb, (7, 7), 1, "fill", cand2d, "u8 2-D k7")
+        emit("u8", 2, 0, 7, b[1])
+    if only is None or "c0" in only or "c2" in only:
+        x, y = precision_pair((4096, 4096), seed=3)
+        for k in (3, 5, 7, 9, 15, 31):
+            b = tune_single(x, y, (k, k), 1, "clip", cand2d, f"f32 2-D k{k}")
+            emit("f32", 2, 0, kbucket(k), b[1])
+    if only is None or "c3" in only:
+        pairs = batched_pairs(64, seed=1, scale=0.5)
+        candb = [(4, th, w) for th, w in itertools.product(ths, wpbs)]
+        b = tune_batch(pairs, candb, "f32 batch")
+        emit("f32", 2, 0, 0, b[1])
+    if only is None or "c4b" in only:
+        x, y = series_1d(1 << 26, seed=5)
+        cand1 = [(8, th, w) for th, w in itertools.product([16, 32, 64, 128, 256], [1, 2])]
+        b = tune_single(x, y, (1001,), 1, "clip", cand1, "f32 1-D k1001")
+        emit("f32", 1, 0, kbucket(1001), b[1])
+    with open(args.out, "w") as f:
+        f.write("# swcorr tuning table: dtype ndim accum kbucket R TH wpb min_waves\n")
+        f.write(f"# written by paper_1807_06507_amd.autotune on "
+                f"{torch.cuda.get_device_name(0)} in {time.time() - t0:.0f} s\n")
+        f.write("\n".join(lines) + "\n")
+    print(open(args.out).read())
+
+
+if __name__ == "__main__":
+    main()

@@ -87,14 +87,16 @@ void load_tune_file(const char* path)
     char line[512];
     while (fgets(line, sizeof line, f)) {
         if (line[0] == '#') continue;
-        int dt, nd, ac, kb, R, TH, wpb, minw;
-        if (sscanf(line, "%d %d %d %d %d %d %d %d", &dt, &nd, &ac, &kb, &R, &TH, &wpb, &minw) == 8) {
+        int dt, nd, ac, kb, R, TH, wpb, minw, ty = 0;
+        if (sscanf(line, "%d %d %d %d %d %d %d %d %d", &dt, &nd, &ac, &kb, &R, &TH, &wpb, &minw,
+                   &ty) >= 8) {
             swc_launch_params lp;
             memset(&lp, 0, sizeof lp);
             lp.cols_per_lane = R;
             lp.tile_rows = TH;
             lp.waves_per_block = wpb;
             lp.min_waves_per_eu = minw;
+            lp.tile_rows2 = ty;
             g_tune[std::make_tuple(dt, nd, ac, kb)] = lp;
         }
     }
@@ -138,11 +140,12 @@ LaunchCfg default_cfg(const swc_problem* p)
     } else if (p->ndim == 1) {
         L.R = 8;
         L.TH = 64;
-        L.wpb = 4;
+        L.wpb = 2;
     } else {
         L.R = 4;
-        L.TH = 16;
-        L.wpb = 4;
+        L.TH = 32;
+        L.wpb = 2;
+        L.TY = 2;
     }
     return L;
 }
@@ -154,6 +157,7 @@ LaunchCfg cfg_from_params(const swc_launch_params* lp)
     L.TH = lp->tile_rows;
     L.wpb = lp->waves_per_block;
     L.minw = lp->min_waves_per_eu;
+    L.TY = lp->tile_rows2;
     return L;
 }
 
@@ -187,6 +191,22 @@ LaunchCfg resolve_cfg(const swc_problem* p)
 }
 
 }  // namespace
+
+namespace swc {
+// Launch configuration of one pair computed outside a persistent batch.
+LaunchCfg batch_pair_cfg(const swc_problem& p) { return resolve_cfg(&p); }
+
+// Tuning-table lookup by raw key (the batch plan uses kbucket 0).
+bool tune_lookup(int dtype, int ndim, int accum, int kb, swc_launch_params* out)
+{
+    ensure_init();
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    auto it = g_tune.find(std::make_tuple(dtype, ndim, accum, kb));
+    if (it == g_tune.end()) return false;
+    *out = it->second;
+    return true;
+}
+}  // namespace swc
 
 extern "C" {
 
@@ -296,6 +316,7 @@ swc_status swc_tune_get(const swc_problem* p, swc_launch_params* lp)
     lp->tile_rows = L.TH;
     lp->waves_per_block = L.wpb;
     lp->min_waves_per_eu = L.minw;
+    lp->tile_rows2 = L.TY;
     return cfg_ok(p, L) ? SWC_OK : SWC_ERR_UNSUPPORTED;
 }
 
@@ -309,6 +330,7 @@ swc_status swc_corr_ex(const swc_problem* p, const swc_launch_params* lp, const 
     LaunchCfg L;
     if (lp && (lp->cols_per_lane || lp->tile_rows || lp->waves_per_block)) {
         L = cfg_from_params(lp);
+        if (p->ndim == 3 && L.TY == 0) L.TY = 2;
         if (!cfg_ok(p, L)) return SWC_ERR_PARAM;
     } else {
         L = resolve_cfg(p);

@@ -1,0 +1,297 @@
+// Batched correlation of many independent 2-D pairs in one persistent launch.
+//
+// A plan turns n problems (different shapes, windows, steps, borders) into a
+// single list of tiles: the tiles of pair i occupy [tile0_i, tile0_i + n_i).
+// The device holds one descriptor per pair (the same tile geometry the
+// single-pair register kernel uses).  One launch of a fixed grid of
+// wavefronts walks the list: wave w takes items w, w + W, w + 2W, ...,
+// finds the pair by binary search over tile0 and runs the tile with the
+// kernel variant of that pair's window width.  Pairs are ordered by
+// (window, alignment) so that waves running at the same time mostly share
+// one code path.  Pairs without a compiled variant are computed by their own
+// launches, issued by the same swc_batch_launch call (still capture-safe:
+// no allocation, copy or synchronisation).
+#include <stdlib.h>
+#include <string.h>
+
+#include <algorithm>
+#include <array>
+#include <vector>
+
+#include "swc_corr2d_fast.hpp"
+#include "swc_internal.h"
+
+namespace swc {
+
+struct BatchItem {
+    P2DF g;
+    int64_t tile0;
+    int kw;
+    int vec;
+    int lds;      // LDS bytes this pair's tiles need per wave
+    int pad;
+};
+
+constexpr int kBatchR = 4;
+
+template <int M, int KW>
+__device__ __forceinline__ void batch_tile(const P2DF& g, int vec, int tile, char* lds)
+{
+    if (vec) tile2d<M, kBatchR, KW, true>(g, tile, lds);
+    else tile2d<M, kBatchR, KW, false>(g, tile, lds);
+}
+
+template <int M>
+__global__ void __launch_bounds__(256)
+__attribute__((amdgpu_waves_per_eu(2, 8))) corr2d_batch_kernel(const BatchItem* __restrict__ items,
+                                                                int n, int64_t total,
+                                                                int64_t nwaves, int lds_stride)
+{
+    extern __shared__ __attribute__((aligned(16))) char smem[];
+    const int wv = threadIdx.x / kWave;
+    const int wpb = blockDim.x / kWave;
+    const int64_t gid = (int64_t)xcd_remap(blockIdx.x, gridDim.x) * wpb + wv;
+    char* lds = smem + (size_t)wv * lds_stride;
+    for (int64_t it = gid; it < total; it += nwaves) {
+        // pair owning item `it` (wave-uniform)
+        int lo = 0, hi = n - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (items[mid].tile0 <= it) lo = mid;
+            else hi = mid - 1;
+        }
+        const BatchItem& b = items[lo];
+        const P2DF g = b.g;
+        const int tile = (int)(it - b.tile0);
+        switch (b.kw) {
+        case 3: batch_tile<M, 3>(g, b.vec, tile, lds); break;
+        case 5: batch_tile<M, 5>(g, b.vec, tile, lds); break;
+        case 7: batch_tile<M, 7>(g, b.vec, tile, lds); break;
+        case 9: batch_tile<M, 9>(g, b.vec, tile, lds); break;
+        case 15: batch_tile<M, 15>(g, b.vec, tile, lds); break;
+        default: break;
+        }
+    }
+}
+
+static bool batch_kw_ok(int kw) { return kw == 3 || kw == 5 || kw == 7 || kw == 9 || kw == 15; }
+
+}  // namespace swc
+
+using namespace swc;
+
+struct swc_batch_plan {
+    int mode;
+    int n_items;
+    int64_t total_tiles;
+    int lds_stride;
+    int wpb;
+    int64_t nwaves;
+    BatchItem* d_items;          // device, owned
+    // pairs computed by their own launches
+    std::vector<swc_problem> rest_p;
+    std::vector<std::array<const void*, 2>> rest_xy;
+    std::vector<float*> rest_c;
+    std::vector<uint8_t*> rest_f;
+    std::vector<std::array<int64_t, 3>> rest_osh;
+    std::vector<LaunchCfg> rest_cfg;
+    int device;
+};
+
+namespace swc {
+// default per-pair configuration chooser (shared with the single-pair path)
+LaunchCfg batch_pair_cfg(const swc_problem& p);
+bool tune_lookup(int dtype, int ndim, int accum, int kb, swc_launch_params* out);
+}
+
+extern "C" {
+
+swc_status swc_batch_plan_create(int32_t n, const swc_problem* p, const void* const* x,
+                                 const void* const* y, float* const* c, uint8_t* const* flags,
+                                 const swc_launch_params* lp, swc_batch_plan** out)
+{
+    if (!out) return SWC_ERR_NULL;
+    *out = nullptr;
+    if (n < 1) return SWC_ERR_SHAPE;
+    if (!p || !x || !y || !c) return SWC_ERR_NULL;
+    const int mode = mode_of(p[0].dtype, p[0].accum);
+    for (int i = 0; i < n; i++) {
+        swc_status st = swc_validate(&p[i]);
+        if (st != SWC_OK) return st;
+        if (p[i].ndim != 2) return SWC_ERR_NDIM;
+        if (p[i].dtype != p[0].dtype) return SWC_ERR_DTYPE;
+        if (p[i].accum != p[0].accum) return SWC_ERR_ACCUM;
+        if (!x[i] || !y[i] || !c[i]) return SWC_ERR_NULL;
+    }
+    int TH = 24, wpb = 2, minw = 0;
+    swc_launch_params tuned;
+    if (!(lp && (lp->tile_rows || lp->waves_per_block)) &&
+        tune_lookup(p[0].dtype, 2, p[0].accum, 0, &tuned))
+        lp = &tuned;
+    if (lp && (lp->tile_rows || lp->waves_per_block)) {
+        if (lp->cols_per_lane && lp->cols_per_lane != kBatchR) return SWC_ERR_PARAM;
+        TH = lp->tile_rows;
+        wpb = lp->waves_per_block;
+        minw = lp->min_waves_per_eu;
+        if (TH < 1 || TH > 4096 || !(wpb == 1 || wpb == 2 || wpb == 4)) return SWC_ERR_PARAM;
+    }
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return SWC_ERR_DEVICE;
+    int cus = 256;
+    hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+
+    swc_batch_plan* plan = new swc_batch_plan();
+    plan->mode = mode;
+    plan->device = dev;
+    plan->wpb = wpb;
+    std::vector<BatchItem> items;
+    std::vector<int> order(n);
+    for (int i = 0; i < n; i++) order[i] = i;
+    // group by (window width, alignment) so concurrent waves share code
+    auto vec_of = [&](int i) {
+        const size_t esz = p[i].dtype == SWC_U8 ? 1 : (p[i].dtype == SWC_U16 ? 2 : 4);
+        const size_t va = esz * kBatchR;
+        return ((uintptr_t)x[i] % va == 0 && (uintptr_t)y[i] % va == 0 &&
+                p[i].shape[1] % kBatchR == 0) ? 1 : 0;
+    };
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+        if (p[a].window[1] != p[b].window[1]) return p[a].window[1] < p[b].window[1];
+        return vec_of(a) > vec_of(b);
+    });
+    int64_t tile0 = 0;
+    int lds_max = 0;
+    for (int oi = 0; oi < n; oi++) {
+        const int i = order[oi];
+        const swc_problem& q = p[i];
+        int64_t osh[3];
+        swc_output_shape(&q, osh);
+        const bool fast = (mode == MODE_U8 || mode == MODE_U16 || mode == MODE_F64) &&
+                          batch_kw_ok(q.window[1]) && q.shape[0] < (1ll << 30) &&
+                          q.shape[1] < (1ll << 30) &&
+                          (int64_t)fast2d_lds_per_wave(mode, kBatchR, q.window[0]) * wpb <=
+                              64 * 1024;
+        LaunchCfg L;
+        L.R = kBatchR;
+        L.TH = TH;
+        L.wpb = wpb;
+        L.minw = minw;
+        if (!fast) {
+            plan->rest_p.push_back(q);
+            plan->rest_xy.push_back({x[i], y[i]});
+            plan->rest_c.push_back(c[i]);
+            plan->rest_f.push_back(flags ? flags[i] : nullptr);
+            plan->rest_osh.push_back({osh[0], osh[1], osh[2]});
+            plan->rest_cfg.push_back(batch_pair_cfg(q));
+            continue;
+        }
+        BatchItem b;
+        memset(&b, 0, sizeof b);
+        P2DF& g = b.g;
+        g.x = x[i];
+        g.y = y[i];
+        g.c = c[i];
+        g.flags = flags ? flags[i] : nullptr;
+        g.H = (int)q.shape[0];
+        g.W = (int)q.shape[1];
+        g.OH = (int)osh[0];
+        g.OW = (int)osh[1];
+        g.kh = q.window[0];
+        g.sh = q.step[0];
+        g.sw = q.step[1];
+        g.oh = window_offset(q.border, q.window[0]);
+        g.ow = window_offset(q.border, q.window[1]);
+        g.border = q.border;
+        g.invalid = q.invalid_value;
+        g.miss_thr = missing_threshold(q.missing_le);
+        g.force = 0;
+        g.TH = TH;
+        const int span = kWave * kBatchR - (kBatchR - 1);
+        g.Wq = (span - q.window[1]) / q.step[1] + 1;
+        const int tiles_x = (int)((osh[1] + g.Wq - 1) / g.Wq);
+        g.tiles_y = (int)((osh[0] + TH - 1) / TH);
+        g.n_tiles = tiles_x * g.tiles_y;
+        const double th_ext = (double)(TH - 1) * q.step[0] + q.window[0];
+        const double chain = 2.0 * th_ext + q.window[1] + 2.0 * kBatchR + 2.0;
+        g.cert_g = cert_factor(mode, (double)q.window[0] * q.window[1], chain,
+                               (double)(q.window[0] + 1) * (q.window[1] + 1));
+        b.tile0 = tile0;
+        b.kw = q.window[1];
+        b.vec = vec_of(i);
+        b.lds = fast2d_lds_per_wave(mode, kBatchR, q.window[0]);
+        lds_max = std::max(lds_max, b.lds);
+        tile0 += g.n_tiles;
+        items.push_back(b);
+    }
+    plan->n_items = (int)items.size();
+    plan->total_tiles = tile0;
+    plan->lds_stride = (lds_max + 15) & ~15;
+    // persistent grid: a few waves per SIMD, never more than the work
+    const int64_t target = (int64_t)cus * 4 * (minw > 0 ? minw : 2);
+    plan->nwaves = std::max<int64_t>(1, std::min<int64_t>(target, tile0));
+    plan->d_items = nullptr;
+    if (!items.empty()) {
+        if (hipMalloc((void**)&plan->d_items, items.size() * sizeof(BatchItem)) != hipSuccess) {
+            delete plan;
+            return SWC_ERR_DEVICE;
+        }
+        if (hipMemcpy(plan->d_items, items.data(), items.size() * sizeof(BatchItem),
+                      hipMemcpyHostToDevice) != hipSuccess) {
+            hipFree(plan->d_items);
+            delete plan;
+            return SWC_ERR_DEVICE;
+        }
+    }
+    *out = plan;
+    return SWC_OK;
+}
+
+swc_status swc_batch_launch(const swc_batch_plan* plan, void* stream)
+{
+    if (!plan) return SWC_ERR_NULL;
+    hipStream_t s = (hipStream_t)stream;
+    if (plan->n_items > 0) {
+        const int grid = (int)((plan->nwaves + plan->wpb - 1) / plan->wpb);
+        const size_t smem = (size_t)plan->lds_stride * plan->wpb;
+        const dim3 blk(plan->wpb * kWave);
+        switch (plan->mode) {
+        case MODE_U8:
+            hipLaunchKernelGGL((corr2d_batch_kernel<MODE_U8>), dim3(grid), blk, smem, s,
+                               plan->d_items, plan->n_items, plan->total_tiles, plan->nwaves,
+                               plan->lds_stride);
+            break;
+        case MODE_U16:
+            hipLaunchKernelGGL((corr2d_batch_kernel<MODE_U16>), dim3(grid), blk, smem, s,
+                               plan->d_items, plan->n_items, plan->total_tiles, plan->nwaves,
+                               plan->lds_stride);
+            break;
+        default:
+            hipLaunchKernelGGL((corr2d_batch_kernel<MODE_F64>), dim3(grid), blk, smem, s,
+                               plan->d_items, plan->n_items, plan->total_tiles, plan->nwaves,
+                               plan->lds_stride);
+            break;
+        }
+        if (hipGetLastError() != hipSuccess) return SWC_ERR_LAUNCH;
+    }
+    for (size_t i = 0; i < plan->rest_p.size(); i++) {
+        hipError_t e = launch_corr2d(plan->rest_p[i], plan->rest_osh[i].data(), plan->rest_cfg[i],
+                                     plan->rest_xy[i][0], plan->rest_xy[i][1], plan->rest_c[i],
+                                     plan->rest_f[i], s, 0);
+        if (e != hipSuccess) return SWC_ERR_LAUNCH;
+    }
+    return SWC_OK;
+}
+
+int64_t swc_batch_plan_items(const swc_batch_plan* plan)
+{
+    if (!plan) return 0;
+    return plan->total_tiles + (int64_t)plan->rest_p.size();
+}
+
+void swc_batch_plan_destroy(swc_batch_plan* plan)
+{
+    if (!plan) return;
+    if (plan->d_items) hipFree(plan->d_items);
+    delete plan;
+}
+
+}  // extern "C"

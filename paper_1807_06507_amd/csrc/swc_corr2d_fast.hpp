@@ -42,8 +42,8 @@ struct P2DF {
 __host__ __device__ inline bool fast2d_supported(int mode, int R, int KW)
 {
     if (mode != MODE_U8 && mode != MODE_U16 && mode != MODE_F64) return false;
-    if (R == 4) return KW == 3 || KW == 5 || KW == 7 || KW == 9;
-    if (R == 8) return KW == 7 || KW == 9 || KW == 15;
+    if (R == 4) return KW == 3 || KW == 5 || KW == 7 || KW == 9 || KW == 15 || KW == 31;
+    if (R == 8) return KW == 7 || KW == 15 || KW == 31;
     return false;
 }
 
@@ -59,7 +59,7 @@ __host__ __device__ inline int fast2d_ring_bytes(int mode, int R, int kh)
 }
 __host__ __device__ inline int fast2d_lds_per_wave(int mode, int R, int kh)
 {
-    const int stash = (mode == MODE_F64) ? 0 : 4 * 8 * R * kWave;
+    const int stash = (mode == MODE_F64) ? 0 : 3 * 8 * R * kWave;
     return ((fast2d_ring_bytes(mode, R, kh) + 15) & ~15) + stash;
 }
 
@@ -206,23 +206,67 @@ template <int M, int R> constexpr int fast2d_depth()
     return 4;
 }
 
+// ---- halo exchange + first window sum ------------------------------------
+// Lane-local column c (0 <= c < R own, c < 0 from lanes to the left, c >= R
+// from lanes to the right).  Columns travel hop by hop through DPP wavefront
+// shifts; each is added to the first window sum S (columns -LH..RH) on
+// arrival, and only the 2(R-1) columns the later slides need are kept:
+// keepL[c + LH] for c in [-LH, -LH + R - 2] (c < 0) and keepR[c - RH - 1]
+// for c in [RH + 1, RH + R - 1] (c >= R).
+template <int M, int R, int KW>
+__device__ __forceinline__ void halo_window(const Col<M> (&V)[R], Col<M>& S,
+                                            Col<M> (&keepL)[R > 1 ? R - 1 : 1],
+                                            Col<M> (&keepR)[R > 1 ? R - 1 : 1])
+{
+    constexpr int LH = KW / 2;
+    constexpr int RH = KW - 1 - LH;
+    constexpr int NHL = (LH + R - 1) / R;
+    constexpr int NHR = (RH + R - 1) / R;
+    col_zero<M>(S);
+#pragma unroll
+    for (int c = 0; c < R; c++)
+        if (c <= RH) col_add<M>(S, V[c]);
+    Col<M> cur[R];
+#pragma unroll
+    for (int j = 0; j < R; j++) cur[j] = V[j];
+#pragma unroll
+    for (int h = 1; h <= NHL; h++) {
+#pragma unroll
+        for (int j = 0; j < R; j++) {
+            if (j < h * R - LH) continue;
+            cur[j] = col_dpp<true, M>(cur[j]);      // V[j] of lane t-h
+            const int c = j - h * R;
+            col_add<M>(S, cur[j]);
+            if (c <= -LH + R - 2) keepL[c + LH] = cur[j];
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < R; j++) cur[j] = V[j];
+#pragma unroll
+    for (int h = 1; h <= NHR; h++) {
+#pragma unroll
+        for (int j = 0; j < R; j++) {
+            if (h * R + j > R + RH - 1) continue;
+            cur[j] = col_dpp<false, M>(cur[j]);     // V[j] of lane t+h
+            const int c = h * R + j;
+            if (c <= RH) col_add<M>(S, cur[j]);
+            if (c >= RH + 1) keepR[c - RH - 1] = cur[j];
+        }
+    }
+}
+
+// One tile of the fused 2-D correlation (see the file comment).  `smem` is
+// this wave's LDS region of fast2d_lds_per_wave(M, R, kh) bytes.
 template <int M, int R, int KW, bool VEC>
-__global__ void __launch_bounds__(256) corr2d_fast_kernel(P2DF g)
+__device__ __forceinline__ void tile2d(const P2DF& g, const int tile, char* smem)
 {
     using T = typename Tr<M>::T;
     constexpr int LH = KW / 2;
     constexpr int RH = KW - 1 - LH;
-    static_assert(LH <= R && RH <= R, "window too wide for single-hop exchange");
     constexpr int D = fast2d_depth<M, R>();
     constexpr int NW = Run<T, R>::NW;
     constexpr bool kFloat = (M == MODE_F64);
-    extern __shared__ __attribute__((aligned(16))) char smem[];
-
     const int lane = threadIdx.x & (kWave - 1);
-    const int wv = threadIdx.x / kWave;
-    const int wpb = blockDim.x / kWave;
-    const int tile = xcd_remap(blockIdx.x, gridDim.x) * wpb + wv;
-    if (tile >= g.n_tiles) return;
 
     // ---- tile geometry (wave-uniform) ----
     const int tx = tile / g.tiles_y;
@@ -239,6 +283,11 @@ __global__ void __launch_bounds__(256) corr2d_fast_kernel(P2DF g)
     const int rlo = max(i0, 0);
     const int rhi = min(i0 + nrows - 1, H - 1);
     const bool rows_inside = (i0 >= 0) && (i0 + nrows - 1 <= H - 1);
+    // Alternate the march direction between vertically adjacent tiles: both
+    // tiles that share a halo band then read it at the same moment (both at
+    // the start or both at the end of their march), so one of them hits L2.
+    const bool up = (ty & 1) != 0;
+    const int i1 = i0 + nrows - 1;
     const bool fill = g.border == BORDER_FILL;
     const bool has_flags = g.flags != nullptr;
 
@@ -258,7 +307,7 @@ __global__ void __launch_bounds__(256) corr2d_fast_kernel(P2DF g)
     const uint32_t lane_boff = VEC ? (uint32_t)((colok & 1u) ? c0 : 0) * (uint32_t)sizeof(T) : 0u;
     uint32_t omask = 0, fillb = 0;
     int qj[R];
-    float ncol[R];
+    double ncol[R];
 #pragma unroll
     for (int j = 0; j < R; j++) {
         const int qs = c0 + j - g.ow - LH;          // = q*sw when column c0+j is a centre
@@ -271,11 +320,11 @@ __global__ void __launch_bounds__(256) corr2d_fast_kernel(P2DF g)
         qj[j] = q;
         const int clo = q * g.sw + g.ow, chi = clo + KW - 1;
         fillb |= (fill && (clo < 0 || chi >= W)) ? (1u << j) : 0u;
-        ncol[j] = (float)(min(chi, W - 1) - max(clo, 0) + 1);
+        ncol[j] = (double)(min(chi, W - 1) - max(clo, 0) + 1);
     }
 
     // ---- per-wave LDS: ring of the last k_h raw rows, zeroed, and a stash ----
-    char* wbase = smem + (size_t)wv * fast2d_lds_per_wave(M, R, kh);
+    char* wbase = smem;
     uint32_t* ringx = (uint32_t*)wbase;                         // [kh][64][NW]
     uint32_t* ringy = ringx + kh * kWave * NW;
     int* ringm = (int*)(ringy + kh * kWave * NW);                // [kh][64] (float input)
@@ -320,17 +369,19 @@ __global__ void __launch_bounds__(256) corr2d_fast_kernel(P2DF g)
 
     Run<T, R> pf[D];
 #pragma unroll
-    for (int u = 0; u < D; u++) issue(i0 + u, pf[u]);
+    for (int u = 0; u < D; u++) issue(up ? i1 - u : i0 + u, pf[u]);
 
     int slot = 0;
     int next_ready = kh - 1;
-    int p = p0;
+    int p = up ? p0 + ph - 1 : p0;
+    const int pstep = up ? -1 : 1;
+    const int rstep = up ? -1 : 1;
     for (int base = 0; base < nrows; base += D) {
 #pragma unroll
         for (int u = 0; u < D; u++) {
             const int li = base + u;
             if (li >= nrows) break;
-            const int row = i0 + li;
+            const int row = up ? i1 - li : i0 + li;
             // ---- current row (zero outside the array) ----
             uint32_t wx[NW], wy[NW];
 #pragma unroll
@@ -351,7 +402,7 @@ __global__ void __launch_bounds__(256) corr2d_fast_kernel(P2DF g)
                 __builtin_memcpy(wx, vx, sizeof(T) * R);
                 __builtin_memcpy(wy, vy, sizeof(T) * R);
             }
-            issue(row + D, pf[u]);
+            issue(row + D * rstep, pf[u]);
             // ---- leaving row from the ring (zeros for the first k_h rows) ----
             const int bw = (slot * kWave + lane) * NW;
             uint32_t ox[NW], oy[NW];
@@ -402,17 +453,16 @@ __global__ void __launch_bounds__(256) corr2d_fast_kernel(P2DF g)
             next_ready += g.sh;
 
             // ---- step 3: window sums along the row ----
-            Col<M> lh[LH > 0 ? LH : 1], rh[RH > 0 ? RH : 1];
-#pragma unroll
-            for (int m = 0; m < LH; m++) lh[m] = col_dpp<true, M>(V[R - LH + m]);
-#pragma unroll
-            for (int m = 0; m < RH; m++) rh[m] = col_dpp<false, M>(V[m]);
-            float Mx = 0.f, My = 0.f;
+            Col<M> S, keepL[R > 1 ? R - 1 : 1], keepR[R > 1 ? R - 1 : 1];
+            halo_window<M, R, KW>(V, S, keepL, keepR);
+            double gx = 0.0, gy = 0.0;   // certification thresholds (float input)
             if constexpr (kFloat) {
-                Mx = fmaxf(hmx, fmaxf(__uint_as_float(dpp_from_left(__float_as_uint(hmx))),
-                                      __uint_as_float(dpp_from_right(__float_as_uint(hmx)))));
-                My = fmaxf(hmy, fmaxf(__uint_as_float(dpp_from_left(__float_as_uint(hmy))),
-                                      __uint_as_float(dpp_from_right(__float_as_uint(hmy)))));
+                const double Mx = (double)fmaxf(hmx, fmaxf(__uint_as_float(dpp_from_left(__float_as_uint(hmx))),
+                                                    __uint_as_float(dpp_from_right(__float_as_uint(hmx)))));
+                const double My = (double)fmaxf(hmy, fmaxf(__uint_as_float(dpp_from_left(__float_as_uint(hmy))),
+                                                    __uint_as_float(dpp_from_right(__float_as_uint(hmy)))));
+                gx = g.cert_g * Mx * Mx;
+                gy = g.cert_g * My * My;
             }
             // wave-uniform row quantities
             const int rlo_w = p * g.sh + g.oh, rhi_w = rlo_w + kh - 1;
@@ -422,13 +472,6 @@ __global__ void __launch_bounds__(256) corr2d_fast_kernel(P2DF g)
             const size_t orow = (size_t)p * (size_t)g.OW;
             float* __restrict__ crow = g.c + orow;
 
-            Col<M> S;
-            col_zero<M>(S);
-#pragma unroll
-            for (int c = -LH; c <= RH; c++) {
-                const Col<M>& v = c < 0 ? lh[c + LH] : (c < R ? V[c] : rh[c - R]);
-                col_add<M>(S, v);
-            }
             uint32_t pending = 0;
             float cvals[R];
             uint8_t fls[R];
@@ -436,52 +479,65 @@ __global__ void __launch_bounds__(256) corr2d_fast_kernel(P2DF g)
             for (int j = 0; j < R; j++) {
                 if (j > 0) {
                     const int ca = j + RH, cs = j - 1 - LH;
-                    const Col<M>& va = ca < R ? V[ca] : rh[ca - R];
-                    const Col<M>& vs = cs < 0 ? lh[cs + LH] : V[cs];
+                    const Col<M>& va = ca < R ? V[ca] : keepR[ca - RH - 1];
+                    const Col<M>& vs = cs < 0 ? keepL[cs + LH] : V[cs];
                     col_add<M>(S, va);
                     col_sub<M>(S, vs);
                 }
                 // ---- step 4: epilogue (branch-free; rare cases deferred) ----
                 const bool fb = row_b || ((fillb >> j) & 1u);
-                const double dn = nrow * (double)ncol[j];
-                uint8_t fl;
+                const double dn = nrow * ncol[j];
+                uint8_t fl = 0;
                 float cv;
                 if constexpr (kFloat) {
                     const double N = __builtin_fma(dn, S.xy, -(S.x * S.y));
                     const double Vx = __builtin_fma(dn, S.xx, -(S.x * S.x));
                     const double Vy = __builtin_fma(dn, S.yy, -(S.y * S.y));
-                    const bool miss = S.miss > 0;
-                    fl = fb ? FL_BORDER : (miss ? FL_MISSING : 0);
-                    const double MX = (double)Mx, MY = (double)My;
-                    const bool cert = (Vx > g.cert_g * MX * MX) && (Vy > g.cert_g * MY * MY);
-                    const bool pend = !fl && (!cert || (g.force & 1));
+                    const bool cert = (Vx > gx) && (Vy > gy);
+                    // FP64 rsqrt estimate (relative error ~2^-23) and one Newton step
+                    const double q = Vx * Vy;
+                    double r = __builtin_amdgcn_rsq(q);
+                    const double e = __builtin_fma(q * r, r, -1.0);
+                    r = r * __builtin_fma(e, -0.5, 1.0);
+                    cv = clamp_unit(N * r);
+                    const bool bad = fb || (S.miss > 0);
+                    if (bad) {
+                        fl = fb ? FL_BORDER : FL_MISSING;
+                        cv = g.invalid;
+                    }
+                    const bool pend = !bad && (!cert || (g.force & 1));
                     pending |= pend ? (1u << j) : 0u;
-                    cv = clamp_unit(N * rsqrt64(Vx * Vy));
                 } else {
                     const double sx = (double)S.x, sy = (double)S.y;
                     const double N = __builtin_fma(0.5 * dn, (double)S.xy2, -(sx * sy));
                     const double Vx = __builtin_fma(dn, (double)S.xx, -(sx * sx));
                     const double Vy = __builtin_fma(dn, (double)S.yy, -(sy * sy));
-                    const uint8_t zv = (Vx == 0.0 ? FL_ZVAR_X : 0) | (Vy == 0.0 ? FL_ZVAR_Y : 0);
-                    fl = fb ? FL_BORDER : zv;
-                    // certified RN32 estimate (see rn32_certified)
+                    // certified RN32 estimate: v_rsq_f64 (relative error well
+                    // below 2^-20) and one Newton step leave < 2^-38; outputs
+                    // whose 29 discarded mantissa bits lie within 2^15 of the
+                    // midpoint pattern take the exact decision
                     const double q = Vx * Vy;
-                    double r = (double)__builtin_amdgcn_rsqf((float)q);
-                    const double e = __builtin_fma((-0.5 * q) * r, r, 0.5);
-                    r = __builtin_fma(r, e, r);
+                    double r = __builtin_amdgcn_rsq(q);
+                    const double e = __builtin_fma(q * r, r, -1.0);
+                    r = r * __builtin_fma(e, -0.5, 1.0);
                     const double a = __builtin_fabs(N) * r;
                     const uint32_t t = (uint32_t)__double_as_longlong(a) & 0x1FFFFFFFu;
                     const bool amb = (t - (0x10000000u - (1u << 15))) <= (2u << 15);
                     const float f = (float)a;
                     cv = (N < 0.0) ? -f : f;
-                    const bool pend = !fl && (N != 0.0) && (amb || (g.force & 1));
+                    const bool bad = fb || (q == 0.0);   // Vx, Vy >= 0 are exact integers
+                    if (bad) {
+                        fl = fb ? FL_BORDER : (uint8_t)((Vx == 0.0 ? FL_ZVAR_X : 0) | (Vy == 0.0 ? FL_ZVAR_Y : 0));
+                        cv = g.invalid;
+                    }
+                    const bool pend = !bad && (amb || (g.force & 1));
                     pending |= pend ? (1u << j) : 0u;
                     if (pend) {
-                        double* st = stash + (size_t)(j * kWave + lane) * 4;
-                        st[0] = N; st[1] = Vx; st[2] = Vy; st[3] = a;
+                        double* st = stash + (size_t)(j * kWave + lane) * 3;
+                        st[0] = N; st[1] = Vx; st[2] = Vy;
                     }
                 }
-                cvals[j] = fl ? g.invalid : cv;
+                cvals[j] = cv;
                 fls[j] = fl;
             }
             // rare path: exact decisions / two-pass recomputation
@@ -499,9 +555,11 @@ __global__ void __launch_bounds__(256) corr2d_fast_kernel(P2DF g)
                         for (int jj = 0; jj < R; jj++)
                             if (jj == j) { fls[jj] = f2; cvals[jj] = f2 ? g.invalid : cvr; }
                     } else {
-                        const double* st = stash + (size_t)(j * kWave + lane) * 4;
+                        const double* st = stash + (size_t)(j * kWave + lane) * 3;
                         const double N = st[0];
-                        float f = rn32_exact_decide(__builtin_fabs(N), st[1], st[2], st[3]);
+                        // any estimate far inside half an ulp selects the right bucket
+                        const double a = __builtin_fabs(N) / __builtin_sqrt(st[1] * st[2]);
+                        float f = rn32_exact_decide(__builtin_fabs(N), st[1], st[2], a);
                         f = N < 0.0 ? -f : f;
 #pragma unroll
                         for (int jj = 0; jj < R; jj++)
@@ -516,9 +574,25 @@ __global__ void __launch_bounds__(256) corr2d_fast_kernel(P2DF g)
                     if (has_flags) g.flags[orow + (uint32_t)qj[j]] = fls[j];
                 }
             }
-            ++p;
+            p += pstep;
         }
     }
+}
+
+// Occupancy target: three waves per SIMD for the integer kernels with R = 4
+// (their register and LDS footprints allow it), two otherwise.
+template <int M, int R> constexpr int fast2d_min_waves() { return (M != MODE_F64 && R == 4) ? 3 : 2; }
+
+template <int M, int R, int KW, bool VEC>
+__global__ void __launch_bounds__(256)
+__attribute__((amdgpu_waves_per_eu(fast2d_min_waves<M, R>(), 8))) corr2d_fast_kernel(P2DF g)
+{
+    extern __shared__ __attribute__((aligned(16))) char smem[];
+    const int wv = threadIdx.x / kWave;
+    const int wpb = blockDim.x / kWave;
+    const int tile = xcd_remap(blockIdx.x, gridDim.x) * wpb + wv;
+    if (tile >= g.n_tiles) return;
+    tile2d<M, R, KW, VEC>(g, tile, smem + (size_t)wv * fast2d_lds_per_wave(M, R, g.kh));
 }
 
 }  // namespace swc

@@ -22,13 +22,15 @@ hipError_t launch_fast2d_modef64(const P2DF& g, int R, int KW, bool vec, int gri
         case 5: return go<4, 5>(g, vec, grid, wpb, smem, s);
         case 7: return go<4, 7>(g, vec, grid, wpb, smem, s);
         case 9: return go<4, 9>(g, vec, grid, wpb, smem, s);
+        case 15: return go<4, 15>(g, vec, grid, wpb, smem, s);
+        case 31: return go<4, 31>(g, vec, grid, wpb, smem, s);
         default: break;
         }
     } else if (R == 8) {
         switch (KW) {
         case 7: return go<8, 7>(g, vec, grid, wpb, smem, s);
-        case 9: return go<8, 9>(g, vec, grid, wpb, smem, s);
         case 15: return go<8, 15>(g, vec, grid, wpb, smem, s);
+        case 31: return go<8, 31>(g, vec, grid, wpb, smem, s);
         default: break;
         }
     }

@@ -1,0 +1,34 @@
+// Instantiations of the fused 3-D kernel for MODE_U8.
+#include "swc_corr3d.hpp"
+#include "swc_internal.h"
+
+namespace swc {
+
+template <int KW, int TY>
+static hipError_t go3(const P3D& g, bool vec, int grid, int wpb, hipStream_t s)
+{
+    if (vec)
+        hipLaunchKernelGGL((corr3d_kernel<MODE_U8, 4, KW, TY, true>), dim3(grid), dim3(wpb * kWave), 0, s, g);
+    else
+        hipLaunchKernelGGL((corr3d_kernel<MODE_U8, 4, KW, TY, false>), dim3(grid), dim3(wpb * kWave), 0, s, g);
+    return hipGetLastError();
+}
+
+template <int TY>
+static hipError_t pick_kw(const P3D& g, int KW, bool vec, int grid, int wpb, hipStream_t s)
+{
+    switch (KW) {
+    case 3: return go3<3, TY>(g, vec, grid, wpb, s);
+    case 5: return go3<5, TY>(g, vec, grid, wpb, s);
+    case 7: return go3<7, TY>(g, vec, grid, wpb, s);
+    case 9: return go3<9, TY>(g, vec, grid, wpb, s);
+    default: return hipErrorNotSupported;
+    }
+}
+
+hipError_t launch_fast3d_modeu8(const P3D& g, int KW, int TY, bool vec, int grid, int wpb, hipStream_t s)
+{
+    return TY == 4 ? pick_kw<4>(g, KW, vec, grid, wpb, s) : pick_kw<2>(g, KW, vec, grid, wpb, s);
+}
+
+}  // namespace swc

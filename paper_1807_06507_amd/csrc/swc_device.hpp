@@ -360,6 +360,7 @@ __device__ inline int u320_cmp(const U320& a, const U320& b)
 // exact value with m decides (ties to even).
 __device__ __noinline__ float rn32_exact_decide(double aN, double Vx, double Vy, double a)
 {
+    if (aN == 0.0) return 0.0f;
     uint64_t bits = (uint64_t)__double_as_longlong(a);
     uint64_t tb = bits & ~0x1FFFFFFFull;                 // trunc to float32 precision
     uint64_t mb = tb | 0x10000000ull;                    // bucket midpoint

@@ -15,6 +15,7 @@ struct LaunchCfg {
     int TH;      // rows (2-D) / planes (3-D) / sample rows (1-D) per tile
     int wpb;     // waves per workgroup
     int minw;    // occupancy hint variant (0 = none)
+    int TY = 0;  // 3-D: output rows per wave (0 = default)
 };
 
 // Kernel mode from (dtype, accum); -1 when the pair is invalid.

@@ -141,8 +141,20 @@ def test_parity_config_small_cloud_pair():
 def test_parity_config_paper_shaped_full():
     """The paper-shaped configuration at full size (4000x3000 u16, 7x7, FILL):
     every output, bit-exact."""
+    import paper_1807_06507_amd as swc
+    from gpu_util import gpu_corr
     x, y = paper_shaped_u16((3000, 4000), seed=2)
     compare(x, y, (7, 7), 1, "fill", tag="c1-full")
+    # every output through the exact big-integer decision: identical bits,
+    # so the certified FP64 estimate never rounded differently (12M samples)
+    a, fa = gpu_corr(x, y, (7, 7), 1, "fill")
+    swc.set_debug(1)
+    try:
+        b, fb = gpu_corr(x, y, (7, 7), 1, "fill")
+    finally:
+        swc.set_debug(0)
+    assert np.array_equal(fa, fb)
+    assert np.array_equal(a.view(np.uint32), b.view(np.uint32))
 
 
 @pytest.mark.parametrize("dtype", ["u8", "u16", "f32"])
