@@ -41,19 +41,30 @@ WORKLOADS = {
                shape=(3000, 4000), dtype="u16", window=(7, 7), step=(1, 1), border="fill"),
     "c0": dict(desc="1024x768 float32 cloud pair, window 7x7, step 1, CLIP",
                shape=(768, 1024), dtype="f32", window=(7, 7), step=(1, 1), border="clip"),
-    "c2": dict(desc="4096x4096 float32 offset pair (precision sweep case k=7, s=1), CLIP",
+    "c2": dict(desc="4096x4096 float32 offset pair (precision case k=7, s=1), CLIP",
                shape=(4096, 4096), dtype="f32", window=(7, 7), step=(1, 1), border="clip"),
+    "c3": dict(desc="64 float32 cloud pairs, 256..4096 x 256..3072, windows {5,7,9,15}, step 1, "
+                    "CLIP, one persistent launch", batched=True, dtype="f32"),
+    "c4a": dict(desc="512x512x256 float32 smoothed-normal volume pair, window 7x7x7, step 1, CLIP",
+                shape=(256, 512, 512), dtype="f32", window=(7, 7, 7), step=(1, 1, 1),
+                border="clip"),
+    "c4b": dict(desc="2^28-sample float32 AR(1) series pair, window 1001, step 1, CLIP",
+                shape=(1 << 28,), dtype="f32", window=(1001,), step=(1,), border="clip"),
 }
 
 
 def _gen(name):
-    from workloads import paper_shaped_u16, cloud_pair, precision_pair
+    from workloads import paper_shaped_u16, cloud_pair, precision_pair, volume_3d, series_1d
     w = WORKLOADS[name]
     if name == "c1":
         return paper_shaped_u16(w["shape"], seed=2)
     if name == "c0":
         return cloud_pair(w["shape"], seed=0)
-    return precision_pair(w["shape"], seed=3)
+    if name == "c2":
+        return precision_pair(w["shape"], seed=3)
+    if name == "c4a":
+        return volume_3d(w["shape"], seed=4)
+    return series_1d(w["shape"][0], seed=5)
 
 
 def _kernel_source_hash():
@@ -68,7 +79,7 @@ def _kernel_source_hash():
 def _traffic_from_profiles(kernel_hash, workload):
     """HBM bytes per launch from committed rocprofv3 counter summaries, only
     when they were taken from the current kernel sources."""
-    path = os.path.join(ROOT, "profiles", f"corr2d_{workload}_pmc.json")
+    path = os.path.join(ROOT, "profiles", f"{workload}_pmc.json")
     if not os.path.exists(path):
         return None
     try:
@@ -90,7 +101,8 @@ def cpu_baseline(x, y, w, budget_s=12.0):
     if env_t and env_t.isdigit():
         threads = min(threads, int(env_t))
     H = x.shape[0]
-    band = max(w["window"][0], min(H, 256))
+    rows_per_band = {1: 1 << 20, 2: 256, 3: 8}[x.ndim]
+    band = max(w["window"][0], min(H, rows_per_band))
     # warm-up (page in, thread pool)
     oracle.corr(x[:band], y[:band], w["window"], w["step"], w["border"], threads=threads)
     done_px, t0 = 0, time.perf_counter()
@@ -105,8 +117,8 @@ def cpu_baseline(x, y, w, budget_s=12.0):
         if el >= budget_s:
             break
     return {"value": done_px / el / 1e9, "unit": "Gpixel/s", "cores": threads, "kind": "oracle",
-            "sample": f"{r} bands of {band} rows x {x.shape[1]} cols of the same image pair "
-                      f"({done_px / 1e6:.1f} MPixel in {el:.1f} s, OpenMP over outputs)"}
+            "sample": f"{r} slabs of {band} x {list(x.shape[1:])} of the same input pair "
+                      f"({done_px / 1e6:.1f} M elements in {el:.1f} s, OpenMP over outputs)"}
 
 
 def copy_ceiling(torch, nbytes=1 << 30, reps=20):
@@ -128,6 +140,78 @@ def copy_ceiling(torch, nbytes=1 << 30, reps=20):
     return 2.0 * nbytes / (ms * 1e-3) / 1e9
 
 
+def _timed(torch, stream, n, fn):
+    """Run fn(i) for i < n with a HIP event pair around every launch on
+    `stream`; returns (wall seconds, per-launch ms array)."""
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for _ in range(n)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(n):
+        ev[i][0].record(stream)
+        fn(i)
+        ev[i][1].record(stream)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    return elapsed, np.array([a.elapsed_time(b) for a, b in ev])
+
+
+def run_batched(args, torch, swc, dev):
+    """The batched workload: one persistent launch over all 64 pairs, against
+    64 per-image launches (eager and captured in one graph)."""
+    from workloads import batched_pairs
+    w = WORKLOADS["c3"]
+    pairs = batched_pairs(64, seed=1)
+    dp = [dict(x=torch.from_numpy(a).to(dev), y=torch.from_numpy(b).to(dev), window=k, step=1,
+               border="clip") for a, b, k in pairs]
+    px = sum(a.size for a, _, _ in pairs)
+    algo_bytes = sum(a.nbytes + b.nbytes + a.size * 4 for a, b, _ in pairs)
+    plan = swc.BatchPlan(dp)
+    stream = torch.cuda.current_stream(dev)
+    for _ in range(args.warmup):
+        plan.launch()
+    elapsed, lms = _timed(torch, stream, args.steps, lambda i: plan.launch())
+    probs = [swc.make_problem(tuple(d["x"].shape), d["x"].dtype, d["window"], 1, "clip")
+             for d in dp]
+
+    def per_image(i):
+        for pr, d, o in zip(probs, dp, plan.outputs):
+            swc.corr_into(pr, d["x"], d["y"], o, None, None, stream)
+    per_image(0)
+    e2, lms2 = _timed(torch, stream, max(3, args.steps // 4), per_image)
+    g = torch.cuda.CUDAGraph()
+    side = torch.cuda.Stream(device=dev)
+    with torch.cuda.graph(g, stream=side):
+        for pr, d, o in zip(probs, dp, plan.outputs):
+            swc.corr_into(pr, d["x"], d["y"], o, None, None, torch.cuda.current_stream(dev))
+    g.replay()
+    e3, lms3 = _timed(torch, stream, max(3, args.steps // 4), lambda i: g.replay())
+    mean_s = float(lms.mean()) * 1e-3
+    line = {
+        "metric": METRIC, "value": round(args.steps * px / elapsed / 1e9, 3), "unit": "Gpixel/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(elapsed / args.steps * 1e3, 5), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": w["desc"], "pairs": 64, "pixels": px,
+                   "work_items": plan.items},
+        "roofline": {"bound": "hbm", "achieved": round(algo_bytes / mean_s / 1e9, 1),
+                     "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+                     "frac": round(algo_bytes / mean_s / 1e9 / HBM_PEAK_GBPS, 4),
+                     "traffic": None},
+        "kernel_ms_mean": round(float(lms.mean()), 5),
+        "per_image_launches_ms": round(float(lms2.mean()), 5),
+        "per_image_graph_ms": round(float(lms3.mean()), 5),
+        "batched_vs_per_image": round(float(lms2.mean()) / float(lms.mean()), 3),
+        "algorithmic_bytes_per_launch": algo_bytes,
+        "kernel_source_hash": _kernel_source_hash(),
+    }
+    if not args.no_cpu:
+        a, b, k = pairs[0]
+        line["cpu_baseline"] = cpu_baseline(a, b, dict(window=(k, k), step=(1, 1),
+                                                       border="clip"))
+    return line
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -137,7 +221,7 @@ def main():
     ap.add_argument("--sets", type=int, default=0, help="buffer sets (0 = auto, > 2x MALL)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-copy", action="store_true", help="skip the copy-ceiling probe")
-    ap.add_argument("--params", default="", help="R,TH,wpb launch parameters override")
+    ap.add_argument("--params", default="", help="R,TH,wpb[,minw,TY] launch parameters")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -153,21 +237,24 @@ def main():
         _b.build()
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = torch.device("cuda:0")
+    if WORKLOADS[args.config].get("batched"):
+        line = run_batched(args, torch, swc, dev)
+        if not args.no_copy:
+            line["copy_ceiling_GBps"] = round(copy_ceiling(torch), 1)
+        print(json.dumps(line), flush=True)
+        return
     w = WORKLOADS[args.config]
     x, y = _gen(args.config)
-    H, W = w["shape"]
     p = swc.make_problem(w["shape"], x.dtype, w["window"], w["step"], w["border"])
     oshape = swc.output_shape(p)
     in_bytes = x.nbytes + y.nbytes
     out_bytes = int(np.prod(oshape)) * 4
     algo_bytes = in_bytes + out_bytes
-    per_set = algo_bytes
-    n_sets = args.sets or max(2, int(np.ceil(2.2 * MALL_BYTES / per_set)))
+    n_sets = args.sets or max(2, int(np.ceil(2.2 * MALL_BYTES / algo_bytes)))
     xd0 = torch.from_numpy(x).to(dev)
     yd0 = torch.from_numpy(y).to(dev)
-    sets = []
-    for i in range(n_sets):
-        sets.append((xd0.clone(), yd0.clone(), torch.empty(oshape, dtype=torch.float32, device=dev)))
+    sets = [(xd0.clone(), yd0.clone(), torch.empty(oshape, dtype=torch.float32, device=dev))
+            for _ in range(n_sets)]
     del xd0, yd0
     params = tuple(int(v) for v in args.params.split(",")) if args.params else None
     stream = torch.cuda.current_stream(dev)
@@ -178,38 +265,25 @@ def main():
 
     for i in range(args.warmup):
         step(i)
-    torch.cuda.synchronize()
-
-    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-          for _ in range(args.steps)]
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for i in range(args.steps):
-        ev[i][0].record(stream)
-        step(i)
-        ev[i][1].record(stream)
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
-    launch_ms = np.array([a.elapsed_time(b) for a, b in ev])
+    elapsed, launch_ms = _timed(torch, stream, args.steps, step)
     mean_launch_s = float(launch_ms.mean()) * 1e-3
 
-    px = H * W
-    value = args.steps * px / elapsed / 1e9
+    n_in = int(np.prod(w["shape"]))
+    value = args.steps * n_in / elapsed / 1e9
     achieved = algo_bytes / mean_launch_s / 1e9
     khash = _kernel_source_hash()
     traffic = _traffic_from_profiles(khash, args.config)
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBPS, 4),
-            "traffic": traffic}
+            "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": traffic}
+    dt = {np.dtype(np.uint16): "u16", np.dtype(np.uint8): "u8"}.get(x.dtype, "f32")
     line = {
         "metric": METRIC, "value": round(value, 3), "unit": "Gpixel/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": round(elapsed / args.steps * 1e3, 5), "higher_is_better": True,
-        "scaling": "weak", "vs_baseline": None, "dtype": "u16" if x.dtype == np.uint16 else str(x.dtype),
-        "data": "synthetic",
+        "scaling": "weak", "vs_baseline": None, "dtype": dt, "data": "synthetic",
         "config": {"workload": w["desc"], "shape": list(w["shape"]), "window": list(w["window"]),
                    "step": list(w["step"]), "border": w["border"], "buffer_sets": n_sets,
-                   "params": swc.tune_get(p) if params is None else list(params)},
+                   "params": list(swc.tune_get(p)) if params is None else list(params)},
         "roofline": roof,
         "kernel_ms_mean": round(float(launch_ms.mean()), 5),
         "kernel_ms_min": round(float(launch_ms.min()), 5),
