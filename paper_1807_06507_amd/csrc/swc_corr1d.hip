@@ -13,8 +13,10 @@
 // Entering values come from HBM (coalesced); the value k positions back is
 // read from a per-wave LDS ring that holds the last k + 64R positions, split
 // into R sub-rings by position mod R so that every LDS access of a wavefront
-// touches consecutive words.  The carry starts from a direct sum of the
-// k positions before the segment.
+// touches consecutive words.  Windows whose ring does not fit in LDS re-read
+// the leaving values from global memory instead (they were read k positions
+// earlier by the same wave and are normally still in L2).  The carry starts
+// from a direct sum of the k positions before the segment.
 #include "swc_device.hpp"
 #include "swc_internal.h"
 
@@ -125,7 +127,7 @@ __device__ __forceinline__ Ch<M> ch_diff(float x, float y, float xo, float yo, i
 
 template <int M, class T> __device__ __forceinline__ float as_val(T v) { return (float)v; }
 
-template <int M>
+template <int M, bool RING>
 __global__ void __launch_bounds__(256) corr1d_kernel(P1D g)
 {
     using T = typename Tr<M>::T;
@@ -179,11 +181,13 @@ __global__ void __launch_bounds__(256) corr1d_kernel(P1D g)
             m = (is_missing(a, g.miss_thr) || is_missing(b, g.miss_thr)) ? 1 : 0;
             if (m) { a = 0.f; b = 0.f; }
         }
-        int sr, si;
-        slot_of(e, sr, si);
-        rx[sr * sub + si] = a;
-        ry[sr * sub + si] = b;
-        rm[sr * sub + si] = (uint8_t)m;
+        if constexpr (RING) {
+            int sr, si;
+            slot_of(e, sr, si);
+            rx[sr * sub + si] = a;
+            ry[sr * sub + si] = b;
+            rm[sr * sub + si] = (uint8_t)m;
+        }
         if (i >= kal - k) {
             Ch<M> d = ch_diff<M>(a, b, 0.f, 0.f, m, 0);
             ch_add<M>(part, d);
@@ -230,26 +234,41 @@ __global__ void __launch_bounds__(256) corr1d_kernel(P1D g)
                 lmy = fmaxf(lmy, __builtin_fabsf(b[j]));
             }
         }
-        // park the entering values first: for k < 64R a position's leaving
-        // value can be an entering value of this same row
-        wave_lds_sync();   // previous row's reads are ordered before these writes
+        if constexpr (RING) {
+            // park the entering values first: for k < 64R a position's
+            // leaving value can be an entering value of this same row
+            wave_lds_sync();   // previous row's reads are ordered before these writes
 #pragma unroll
-        for (int j = 0; j < R; j++) {
-            int sr, si;
-            slot_of(e0 + j, sr, si);
-            rx[sr * sub + si] = a[j];
-            ry[sr * sub + si] = b[j];
-            rm[sr * sub + si] = (uint8_t)m[j];
-        }
-        wave_lds_sync();
-        // leaving values (k positions back) from the ring
+            for (int j = 0; j < R; j++) {
+                int sr, si;
+                slot_of(e0 + j, sr, si);
+                rx[sr * sub + si] = a[j];
+                ry[sr * sub + si] = b[j];
+                rm[sr * sub + si] = (uint8_t)m[j];
+            }
+            wave_lds_sync();
+            // leaving values (k positions back) from the ring
 #pragma unroll
-        for (int j = 0; j < R; j++) {
-            int sr, si;
-            slot_of(e0 + j - k, sr, si);
-            ao[j] = rx[sr * sub + si];
-            bo[j] = ry[sr * sub + si];
-            mo[j] = rm[sr * sub + si];
+            for (int j = 0; j < R; j++) {
+                int sr, si;
+                slot_of(e0 + j - k, sr, si);
+                ao[j] = rx[sr * sub + si];
+                bo[j] = ry[sr * sub + si];
+                mo[j] = rm[sr * sub + si];
+            }
+        } else {
+            // leaving values re-read from global memory
+#pragma unroll
+            for (int j = 0; j < R; j++) {
+                ao[j] = load_val(X, e0 + j - k);
+                bo[j] = load_val(Y, e0 + j - k);
+                mo[j] = 0;
+                if constexpr (kFloat) {
+                    mo[j] = (is_missing(ao[j], g.miss_thr) || is_missing(bo[j], g.miss_thr)) ? 1 : 0;
+                    ao[j] = mo[j] ? 0.f : ao[j];
+                    bo[j] = mo[j] ? 0.f : bo[j];
+                }
+            }
         }
         if constexpr (kFloat) {
             MX = fmaxf(MX, wave_max(lmx));
@@ -355,21 +374,28 @@ static size_t lds_per_wave_1d(int mode, int k)
     return (size_t)ring_positions(k) * (mode >= MODE_F64 ? 9 : 8);
 }
 
+// The LDS ring is used when it fits in 64 KB per workgroup.
+static bool ring_fits_1d(int mode, int k, int wpb)
+{
+    return lds_per_wave_1d(mode, k) * (size_t)wpb <= 64 * 1024;
+}
+
 bool cfg_ok_1d(const swc_problem& p, const LaunchCfg& L)
 {
     const int mode = mode_of(p.dtype, p.accum);
     if (mode != MODE_U8 && mode != MODE_U16 && mode != MODE_F64) return false;
     if (!(L.wpb == 1 || L.wpb == 2 || L.wpb == 4)) return false;
     if (L.TH < 1 || L.TH > (1 << 20)) return false;
-    if (L.R != kR1) return false;
-    if (lds_per_wave_1d(mode, p.window[0]) * (size_t)L.wpb > 64 * 1024) return false;
-    return true;
+    return L.R == kR1;
 }
 
 template <int M>
 static hipError_t go1d(const P1D& g, int grid, int wpb, size_t smem, hipStream_t s)
 {
-    hipLaunchKernelGGL((corr1d_kernel<M>), dim3(grid), dim3(wpb * kWave), smem, s, g);
+    if (smem)
+        hipLaunchKernelGGL((corr1d_kernel<M, true>), dim3(grid), dim3(wpb * kWave), smem, s, g);
+    else
+        hipLaunchKernelGGL((corr1d_kernel<M, false>), dim3(grid), dim3(wpb * kWave), 0, s, g);
     return hipGetLastError();
 }
 
@@ -402,7 +428,8 @@ hipError_t launch_corr1d(const swc_problem& p, const int64_t* oshape, const Laun
     g.cert_g = cert_factor(mode, (double)g.k, chain, (double)g.k + 3.0);
     const int64_t grid64 = (g.n_waves + L.wpb - 1) / L.wpb;
     if (grid64 >= ((int64_t)1 << 31)) return hipErrorInvalidValue;
-    const size_t smem = lds_per_wave_1d(mode, g.k) * (size_t)L.wpb;
+    const size_t smem =
+        ring_fits_1d(mode, g.k, L.wpb) ? lds_per_wave_1d(mode, g.k) * (size_t)L.wpb : 0;
     switch (mode) {
     case MODE_U8: return go1d<MODE_U8>(g, (int)grid64, L.wpb, smem, s);
     case MODE_U16: return go1d<MODE_U16>(g, (int)grid64, L.wpb, smem, s);
