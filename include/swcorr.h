@@ -114,7 +114,9 @@ typedef struct swc_problem {
  *   cols_per_lane: contiguous-axis elements owned by one lane (1, 2, 4, 8;
  *                  the 1-D kernel uses 8, the 3-D and batched kernels 4)
  *   tile_rows:     output rows (2-D) / output planes (3-D) / rows of
- *                  64*cols_per_lane window positions (1-D) per wavefront
+ *                  64*cols_per_lane window positions (1-D) per wavefront;
+ *                  2-D: 0 = as many rows as fill the GPU's resident
+ *                  wavefront slots in one round
  *   waves_per_block: 1, 2 or 4 wavefronts per workgroup
  *   min_waves_per_eu: occupancy hint (0 = kernel default)
  *   tile_rows2:    3-D only: output rows per wavefront (2 or 4; 0 = 2)  */

@@ -22,7 +22,9 @@ __all__ = [
 ]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-_LIB_PATH = os.path.join(_HERE, "libswcorr.so")
+# SWC_LIBRARY selects another build of the same library (e.g. a variant
+# compiled with different tuning macros); the default is the in-tree build.
+_LIB_PATH = os.environ.get("SWC_LIBRARY") or os.path.join(_HERE, "libswcorr.so")
 
 U8, U16, F32 = 0, 1, 2
 BORDERS = {"fill": 0, "clip": 1, "valid": 2}

@@ -2,6 +2,8 @@
 
     python -m paper_1807_06507_amd.build          # compile everything
     python -m paper_1807_06507_amd.build --check  # compile, then list symbols
+    python -m paper_1807_06507_amd.build --out DIR/libswcorr.so -DNAME=VALUE ...
+                                                  # a variant build elsewhere
 
 Every translation unit under csrc/ is compiled by hipcc for gfx950 into
 _build/, then linked into paper_1807_06507_amd/libswcorr.so next to this file.
@@ -42,34 +44,42 @@ def sources():
                   if f.endswith(".hip") or f.endswith(".cpp"))
 
 
-def _compile(src):
-    obj = os.path.join(BUILD, os.path.basename(src) + ".o")
+def _compile(src, build_dir=BUILD, defines=()):
+    obj = os.path.join(build_dir, os.path.basename(src) + ".o")
     lang = ["-x", "hip"] if src.endswith(".hip") else []
-    cmd = [_hipcc()] + HIP_FLAGS + lang + ["-c", src, "-o", obj]
+    cmd = [_hipcc()] + HIP_FLAGS + list(defines) + lang + ["-c", src, "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"compile failed: {' '.join(cmd)}\n{r.stdout}\n{r.stderr}")
     return obj
 
 
-def build(verbose: bool = False) -> str:
-    os.makedirs(BUILD, exist_ok=True)
+def build(verbose: bool = False, out: str = LIB, defines=()) -> str:
+    """Compile every source and link `out` (default: the in-tree library).
+    `defines` are extra -D options; a build with any goes to its own object
+    directory next to `out`."""
+    build_dir = BUILD if not defines and out == LIB else out + ".objs"
+    os.makedirs(build_dir, exist_ok=True)
     srcs = sources()
     with cf.ThreadPoolExecutor(max_workers=min(8, len(srcs))) as ex:
-        objs = list(ex.map(_compile, srcs))
-    tmp = LIB + ".tmp%d" % os.getpid()
+        objs = list(ex.map(lambda f: _compile(f, build_dir, defines), srcs))
+    LIB_OUT = out
+    tmp = LIB_OUT + ".tmp%d" % os.getpid()
     cmd = [_hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp] + objs + ["-ldl"]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"link failed: {' '.join(cmd)}\n{r.stdout}\n{r.stderr}")
-    os.replace(tmp, LIB)
+    os.replace(tmp, LIB_OUT)
     if verbose:
-        print(f"built {LIB}")
-    return LIB
+        print(f"built {LIB_OUT}")
+    return LIB_OUT
 
 
 if __name__ == "__main__":
-    build(verbose=True)
+    _out = LIB
+    if "--out" in sys.argv:
+        _out = os.path.abspath(sys.argv[sys.argv.index("--out") + 1])
+    build(verbose=True, out=_out, defines=[a for a in sys.argv[1:] if a.startswith("-D")])
     if "--check" in sys.argv:
         out = subprocess.run(["nm", "-D", "--defined-only", LIB], capture_output=True, text=True)
         print("\n".join(l for l in out.stdout.splitlines() if " swc_" in l))

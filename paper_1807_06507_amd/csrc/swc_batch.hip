@@ -48,7 +48,7 @@ __attribute__((amdgpu_waves_per_eu(2, 8))) corr2d_batch_kernel(const BatchItem* 
                                                                 int64_t nwaves, int lds_stride)
 {
     extern __shared__ __attribute__((aligned(16))) char smem[];
-    const int wv = threadIdx.x / kWave;
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);   // wave-uniform
     const int wpb = blockDim.x / kWave;
     const int64_t gid = (int64_t)xcd_remap(blockIdx.x, gridDim.x) * wpb + wv;
     char* lds = smem + (size_t)wv * lds_stride;
@@ -167,7 +167,7 @@ swc_status swc_batch_plan_create(int32_t n, const swc_problem* p, const void* co
         swc_output_shape(&q, osh);
         const bool fast = (mode == MODE_U8 || mode == MODE_U16 || mode == MODE_F64) &&
                           batch_kw_ok(q.window[1]) && q.shape[0] < (1ll << 30) &&
-                          q.shape[1] < (1ll << 30) &&
+                          q.shape[1] < (1ll << 28) &&   // rows are raw buffers (< 2^31 bytes)
                           (int64_t)fast2d_lds_per_wave(mode, kBatchR, q.window[0]) * wpb <=
                               64 * 1024;
         LaunchCfg L;
@@ -205,8 +205,13 @@ swc_status swc_batch_plan_create(int32_t n, const swc_problem* p, const void* co
         g.miss_thr = missing_threshold(q.missing_le);
         g.force = 0;
         g.TH = TH;
+        const bool contig = q.step[1] == 1 && g.ow == -(q.window[1] / 2);
+        g.vst = (contig && g.OW % 4 == 0 && (uintptr_t)c[i] % 16 == 0 ? 1 : 0) |
+                (contig && g.flags && g.OW % kBatchR == 0 &&
+                 (uintptr_t)g.flags % kBatchR == 0 ? 2 : 0);
         const int span = kWave * kBatchR - (kBatchR - 1);
-        g.Wq = (span - q.window[1]) / q.step[1] + 1;
+        g.Wq = contig ? fast2d_wq_aligned(kBatchR, q.window[1])
+                      : (span - q.window[1]) / q.step[1] + 1;
         const int tiles_x = (int)((osh[1] + g.Wq - 1) / g.Wq);
         g.tiles_y = (int)((osh[0] + TH - 1) / TH);
         g.n_tiles = tiles_x * g.tiles_y;

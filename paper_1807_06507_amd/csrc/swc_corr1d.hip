@@ -135,7 +135,7 @@ __global__ void __launch_bounds__(256) corr1d_kernel(P1D g)
     constexpr bool kFloat = !Tr<M>::kInt;
     extern __shared__ __attribute__((aligned(16))) char smem[];
     const int lane = threadIdx.x & (kWave - 1);
-    const int wv = threadIdx.x / kWave;
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);   // wave-uniform
     const int wpb = blockDim.x / kWave;
     const int64_t w = (int64_t)xcd_remap(blockIdx.x, gridDim.x) * wpb + wv;
     if (w >= g.n_waves) return;

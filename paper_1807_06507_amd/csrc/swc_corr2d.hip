@@ -20,6 +20,11 @@
 #include "swc_device.hpp"
 #include "swc_internal.h"
 
+#include <algorithm>
+#include <map>
+#include <mutex>
+#include <tuple>
+
 namespace swc {
 
 struct P2D {
@@ -63,7 +68,7 @@ __global__ void __launch_bounds__(256) corr2d_kernel(P2D g)
     constexpr int NC = kWave * R;
     extern __shared__ __attribute__((aligned(16))) char smem[];
     const int lane = threadIdx.x & (kWave - 1);
-    const int wv = threadIdx.x / kWave;
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);   // wave-uniform
     const int wpb = blockDim.x / kWave;
     const int tile = xcd_remap(blockIdx.x, gridDim.x) * wpb + wv;
     if (tile >= g.n_tiles) return;
@@ -232,7 +237,7 @@ bool cfg_ok_2d(const swc_problem& p, const LaunchCfg& L)
 {
     if (!(L.R == 1 || L.R == 2 || L.R == 4 || L.R == 8)) return false;
     if (!(L.wpb == 1 || L.wpb == 2 || L.wpb == 4)) return false;
-    if (L.TH < 1 || L.TH > 4096) return false;
+    if (L.TH < 0 || L.TH > 4096) return false;   // 0: chosen per launch
     if (wq_of(L.R, p.window[1], p.step[1]) < 1) return false;
     int mode = mode_of(p.dtype, p.accum);
     if (mode < 0) return false;
@@ -259,6 +264,42 @@ static hipError_t launch_m(const P2D& g, int R, int wpb, int grid, hipStream_t s
     }
 }
 
+// Workgroups of the register-resident kernel that fit on one CU (cached per
+// configuration and device).
+static int fast2d_blocks_per_cu(int mode, int R, int kw, bool vec, int wpb, size_t smem)
+{
+    static std::mutex mu;
+    static std::map<std::tuple<int, int, int, int, int, int, size_t>, int> cache;
+    int dev = 0;
+    hipGetDevice(&dev);
+    const auto key = std::make_tuple(dev, mode, R, kw, (int)vec, wpb, smem);
+    {
+        std::lock_guard<std::mutex> lk(mu);
+        auto it = cache.find(key);
+        if (it != cache.end()) return it->second;
+    }
+    int n = 0;
+    P2DF dummy{};
+    hipError_t e;
+    if (mode == MODE_U8) e = launch_fast2d_modeu8(dummy, R, kw, vec, 0, wpb, smem, nullptr, &n);
+    else if (mode == MODE_U16) e = launch_fast2d_modeu16(dummy, R, kw, vec, 0, wpb, smem, nullptr, &n);
+    else e = launch_fast2d_modef64(dummy, R, kw, vec, 0, wpb, smem, nullptr, &n);
+    if (e != hipSuccess || n < 1) n = 1;
+    std::lock_guard<std::mutex> lk(mu);
+    cache[key] = n;
+    return n;
+}
+
+static int device_cus()
+{
+    int dev = 0, cus = 0;
+    hipGetDevice(&dev);
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        cus < 1)
+        cus = 256;
+    return cus;
+}
+
 hipError_t launch_corr2d(const swc_problem& p, const int64_t* oshape, const LaunchCfg& L,
                          const void* x, const void* y, float* c, uint8_t* flags,
                          hipStream_t s, int force)
@@ -283,29 +324,17 @@ hipError_t launch_corr2d(const swc_problem& p, const int64_t* oshape, const Laun
     g.invalid = p.invalid_value;
     g.miss_thr = missing_threshold(p.missing_le);
     g.force = force;
-    g.TH = L.TH;
-    g.Wq = wq_of(L.R, g.kw, g.sw);
-    g.tiles_x = (int)((g.OW + g.Wq - 1) / g.Wq);
-    g.tiles_y = (int)((g.OH + g.TH - 1) / g.TH);
-    const int64_t nt = (int64_t)g.tiles_x * g.tiles_y;
-    if (nt >= (int64_t)1 << 31) return hipErrorInvalidValue;
-    g.n_tiles = (int)nt;
     const size_t esz = p.dtype == SWC_U8 ? 1 : (p.dtype == SWC_U16 ? 2 : 4);
     const size_t va = esz * (size_t)L.R;
     g.vec = ((uintptr_t)x % va == 0 && (uintptr_t)y % va == 0 && (g.W % L.R) == 0) ? 1 : 0;
-    // certification factor: chain = vertical march (2 ops/row) + horizontal
-    // slide; nterms = (kh+1)(kw+1)
-    const double th_ext = (double)(g.TH - 1) * g.sh + g.kh;
-    const double ro = (double)((g.Wq + kWave - 1) / kWave);
-    const double chain = 2.0 * th_ext + g.kw + 2.0 * ro * g.sw + 2.0;
-    const double nterms = (double)(g.kh + 1) * (g.kw + 1);
-    g.cert_g = cert_factor(mode, (double)g.kh * g.kw, chain, nterms);
-    const int grid = (int)((nt + L.wpb - 1) / L.wpb);
+
     // register-resident kernel for compiled window widths (debug bit 2 forces
-    // the generic LDS kernel)
-    const bool dims32 = g.H < ((int64_t)1 << 31) - 2 * kWave * 8 && g.W < ((int64_t)1 << 31) - 2 * kWave * 8;
-    if (!(force & 2) && dims32 && fast2d_supported(mode, L.R, g.kw) &&
-        (int64_t)L.wpb * fast2d_lds_per_wave(mode, L.R, g.kh) <= 64 * 1024) {
+    // the generic LDS kernel); 32-bit geometry and byte counts (rows are
+    // addressed as raw buffers of at most 2^31 - 1 bytes)
+    const bool dims32 = g.H < ((int64_t)1 << 31) - 2 * kWave * 8 &&
+                        g.W * 4 < ((int64_t)1 << 31) - 2 * kWave * 8 * 4;
+    const size_t smem_f = (size_t)L.wpb * fast2d_lds_per_wave(mode, L.R, g.kh);
+    if (!(force & 2) && dims32 && fast2d_supported(mode, L.R, g.kw) && smem_f <= 64 * 1024) {
         P2DF f;
         f.x = x;
         f.y = y;
@@ -324,17 +353,58 @@ hipError_t launch_corr2d(const swc_problem& p, const int64_t* oshape, const Laun
         f.invalid = g.invalid;
         f.miss_thr = g.miss_thr;
         f.force = force;
-        f.cert_g = g.cert_g;
-        f.TH = g.TH;
-        f.Wq = g.Wq;
-        f.tiles_y = g.tiles_y;
-        f.n_tiles = g.n_tiles;
+        // whole-vector stores: unit column step, centred windows (output
+        // column = input column), rows of a multiple of 4 (c) / R (flags)
+        // elements, aligned bases; tiles then start on lane boundaries
+        const bool contig = g.sw == 1 && g.ow == -(g.kw / 2) && (L.R % 4) == 0 &&
+                            fast2d_wq_aligned(L.R, g.kw) >= 1;
+        f.vst = (contig && g.OW % 4 == 0 && (uintptr_t)c % 16 == 0 ? 1 : 0) |
+                (contig && flags && g.OW % L.R == 0 && (uintptr_t)flags % L.R == 0 ? 2 : 0);
+        f.Wq = contig ? fast2d_wq_aligned(L.R, g.kw) : wq_of(L.R, g.kw, g.sw);
+        const int64_t tiles_x = (g.OW + f.Wq - 1) / f.Wq;
         const bool vec = g.vec != 0;
-        const size_t smem = (size_t)L.wpb * fast2d_lds_per_wave(mode, L.R, g.kh);
-        if (mode == MODE_U8) return launch_fast2d_modeu8(f, L.R, g.kw, vec, grid, L.wpb, smem, s);
-        if (mode == MODE_U16) return launch_fast2d_modeu16(f, L.R, g.kw, vec, grid, L.wpb, smem, s);
-        return launch_fast2d_modef64(f, L.R, g.kw, vec, grid, L.wpb, smem, s);
+        int TH = L.TH;
+        if (TH <= 0) {
+            // one round of resident waves: as many tile rows as the free wave
+            // slots allow across the tile columns, each as tall as that needs
+            const int64_t slots = (int64_t)device_cus() * L.wpb *
+                                  fast2d_blocks_per_cu(mode, L.R, g.kw, vec, L.wpb, smem_f);
+            const int64_t ty = std::max<int64_t>(1, slots / std::max<int64_t>(1, tiles_x));
+            TH = (int)std::min<int64_t>(4096, std::max<int64_t>(4, (g.OH + ty - 1) / ty));
+        }
+        f.TH = TH;
+        f.tiles_y = (int)((g.OH + TH - 1) / TH);
+        const int64_t ntf = tiles_x * f.tiles_y;
+        if (ntf >= (int64_t)1 << 31) return hipErrorInvalidValue;
+        f.n_tiles = (int)ntf;
+        // certification factor: chain = vertical march (2 ops/row) + the
+        // horizontal sums; nterms = (kh+1)(kw+1)
+        const double th_ext = (double)(TH - 1) * g.sh + g.kh;
+        const double chain = 2.0 * th_ext + 2.0 * g.kw + 2.0 * L.R + 2.0;
+        const double nterms = (double)(g.kh + 1) * (g.kw + 1);
+        f.cert_g = cert_factor(mode, (double)g.kh * g.kw, chain, nterms);
+        const int gridf = (int)((ntf + L.wpb - 1) / L.wpb);
+        if (mode == MODE_U8) return launch_fast2d_modeu8(f, L.R, g.kw, vec, gridf, L.wpb, smem_f, s);
+        if (mode == MODE_U16) return launch_fast2d_modeu16(f, L.R, g.kw, vec, gridf, L.wpb, smem_f, s);
+        return launch_fast2d_modef64(f, L.R, g.kw, vec, gridf, L.wpb, smem_f, s);
     }
+
+    // generic LDS-row kernel
+    g.TH = L.TH > 0 ? L.TH : 32;
+    g.Wq = wq_of(L.R, g.kw, g.sw);
+    g.tiles_x = (int)((g.OW + g.Wq - 1) / g.Wq);
+    g.tiles_y = (int)((g.OH + g.TH - 1) / g.TH);
+    const int64_t nt = (int64_t)g.tiles_x * g.tiles_y;
+    if (nt >= (int64_t)1 << 31) return hipErrorInvalidValue;
+    g.n_tiles = (int)nt;
+    // certification factor: chain = vertical march (2 ops/row) + horizontal
+    // slide; nterms = (kh+1)(kw+1)
+    const double th_ext = (double)(g.TH - 1) * g.sh + g.kh;
+    const double ro = (double)((g.Wq + kWave - 1) / kWave);
+    const double chain = 2.0 * th_ext + g.kw + 2.0 * ro * g.sw + 2.0;
+    const double nterms = (double)(g.kh + 1) * (g.kw + 1);
+    g.cert_g = cert_factor(mode, (double)g.kh * g.kw, chain, nterms);
+    const int grid = (int)((nt + L.wpb - 1) / L.wpb);
     switch (mode) {
     case MODE_U8: return launch_m<MODE_U8>(g, L.R, L.wpb, grid, s);
     case MODE_U16: return launch_m<MODE_U16>(g, L.R, L.wpb, grid, s);

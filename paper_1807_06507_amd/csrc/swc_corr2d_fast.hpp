@@ -36,6 +36,7 @@ struct P2DF {
     int force;
     double cert_g;
     int TH, Wq, tiles_y, n_tiles;
+    int vst;                   // bit 0: whole-vector stores of c, bit 1: of flags
 };
 
 // Which (mode, R, KW) combinations have a compiled register-resident kernel.
@@ -47,9 +48,7 @@ __host__ __device__ inline bool fast2d_supported(int mode, int R, int KW)
     return false;
 }
 
-// LDS bytes per wave: the raw-row ring (k_h rows) plus, for integer input,
-// a stash of (N, Vx, Vy, estimate) for outputs that take the exact
-// rounding decision.
+// LDS bytes per wave: the raw-row ring (k_h rows).
 __host__ __device__ inline int fast2d_ring_bytes(int mode, int R, int kh)
 {
     const int esz = mode == MODE_U8 ? 1 : (mode == MODE_U16 ? 2 : 4);
@@ -59,19 +58,33 @@ __host__ __device__ inline int fast2d_ring_bytes(int mode, int R, int kh)
 }
 __host__ __device__ inline int fast2d_lds_per_wave(int mode, int R, int kh)
 {
-    const int stash = (mode == MODE_F64) ? 0 : 3 * 8 * R * kWave;
-    return ((fast2d_ring_bytes(mode, R, kh) + 15) & ~15) + stash;
+    return (fast2d_ring_bytes(mode, R, kh) + 15) & ~15;
 }
 
+// Output columns per tile when outputs are lane-aligned (unit column step,
+// centred windows): whole lanes of halo on each side, so every output lane
+// holds R outputs and stores them as vectors.
+__host__ __device__ inline int fast2d_wq_aligned(int R, int kw)
+{
+    const int lh = kw / 2, rh = kw - 1 - lh;
+    const int h = ((lh > rh ? lh : rh) + R - 1) / R;
+    return (kWave - 2 * h) * R;
+}
+
+// Buffer descriptor word 3 for raw (untyped) buffer access on gfx9-family
+// GPUs; an access whose offset is at or beyond the record count is dropped
+// (stores) or returns zero (loads).
+constexpr int kBufWord3 = 0x00020000;
+constexpr uint32_t kOffNone = 0x80000000u;   // offset that is always out of range
+
+// Launch the kernel for (R, KW, vec), or with occ != nullptr only report how
+// many of its workgroups (wpb waves, smem bytes of LDS) fit on one CU.
 hipError_t launch_fast2d_modeu8(const P2DF& g, int R, int KW, bool vec, int grid, int wpb,
-                                size_t smem,
-                                hipStream_t s);
+                                size_t smem, hipStream_t s, int* occ = nullptr);
 hipError_t launch_fast2d_modeu16(const P2DF& g, int R, int KW, bool vec, int grid, int wpb,
-                                size_t smem,
-                                 hipStream_t s);
+                                 size_t smem, hipStream_t s, int* occ = nullptr);
 hipError_t launch_fast2d_modef64(const P2DF& g, int R, int KW, bool vec, int grid, int wpb,
-                                size_t smem,
-                                 hipStream_t s);
+                                 size_t smem, hipStream_t s, int* occ = nullptr);
 
 // ---- DPP wavefront shifts (lane i <- lane i-1 / lane i+1) -----------------
 __device__ __forceinline__ uint32_t dpp_from_left(uint32_t v)
@@ -255,17 +268,180 @@ __device__ __forceinline__ void halo_window(const Col<M> (&V)[R], Col<M>& S,
     }
 }
 
+// Window sums of one output row along the contiguous axis: S_0 from the
+// halo exchange, then S_{j+1} = S_j + V[j+RH+1] - V[j-LH]; emit(j, S_j) for
+// every lane column j in order.
+template <int M, int R, int KW, class Emit>
+__device__ __forceinline__ void hslide(const Col<M> (&V)[R], Emit&& emit)
+{
+    constexpr int LH = KW / 2;
+    constexpr int RH = KW - 1 - LH;
+    Col<M> S, keepL[R > 1 ? R - 1 : 1], keepR[R > 1 ? R - 1 : 1];
+    halo_window<M, R, KW>(V, S, keepL, keepR);
+#pragma unroll
+    for (int j = 0; j < R; j++) {
+        if (j > 0) {
+            const int ca = j + RH, cs = j - 1 - LH;
+            const Col<M>& va = ca < R ? V[ca] : keepR[ca - RH - 1];
+            const Col<M>& vs = cs < 0 ? keepL[cs + LH] : V[cs];
+            col_add<M>(S, va);
+            col_sub<M>(S, vs);
+        }
+        emit(j, S);
+    }
+}
+
+// Window sums of one output row when the halo reaches only the adjacent
+// lanes (k_w/2 <= R): each lane sends its right neighbour the sums of its
+// last 1..LH columns and its left neighbour the sums of its first 1..RH
+// columns (DPP), then forms
+//   outputs 0..LH      from a prefix chain over its own columns plus the
+//                      received left sums (and right sums once the window
+//                      passes the lane's last column),
+//   outputs near R-1   from a suffix chain plus the received right sums,
+//   any in between     by sliding.
+// Only additions are used outside the middle block, and no partial sum
+// holds a column outside the output's window.
+template <int M, int R, int KW>
+__host__ __device__ constexpr bool hsum_one_hop()
+{
+    return KW / 2 <= R && KW - 1 - KW / 2 <= R && KW >= 3;
+}
+
+template <int M, int R, int KW, class Emit>
+__device__ __forceinline__ void hsum_onehop(const Col<M> (&V)[R], Emit&& emit)
+{
+    constexpr int LH = KW / 2;
+    constexpr int RH = KW - 1 - LH;
+    constexpr int JL = LH < R - 1 ? LH : R - 1;                   // last left-block output
+    constexpr int JR = (R - 1 - RH) > (JL + 1) ? (R - 1 - RH) : (JL + 1);  // first right-block output
+    // sums of this lane's last m columns -> Lx[m] of the right neighbour
+    Col<M> Lx[LH + 1];
+    Col<M> suf = V[R - 1];
+#pragma unroll
+    for (int m = 1; m <= LH; m++) {
+        if (m > 1) col_add<M>(suf, V[R - m]);
+        Lx[m] = col_dpp<true, M>(suf);
+    }
+    // sums of this lane's first m columns -> Rx[m] of the left neighbour
+    Col<M> Rx[RH + 1];
+    Col<M> pre = V[0];
+#pragma unroll
+    for (int m = 1; m <= RH; m++) {
+        if (m > 1 && m <= R) col_add<M>(pre, V[m - 1]);
+        Rx[m] = col_dpp<false, M>(pre);
+    }
+    // left block: own columns 0..min(j+RH, R-1)
+    Col<M> last;
+    {
+        Col<M> P = pre;                       // V[0 .. min(RH, R) - 1]
+#pragma unroll
+        for (int j = 0; j <= JL; j++) {
+            const int b = j + RH;
+            if (b <= R - 1) col_add<M>(P, V[b]);
+            Col<M> S = P;
+            if (j < LH) col_add<M>(S, Lx[LH - j]);
+            if (b > R - 1) col_add<M>(S, Rx[b - R + 1]);
+            emit(j, S);
+            if (j == JL) last = S;
+        }
+    }
+    // middle block: windows strictly inside the lane
+#pragma unroll
+    for (int j = JL + 1; j < JR; j++) {
+        col_add<M>(last, V[j + RH]);
+        col_sub<M>(last, V[j - 1 - LH]);
+        emit(j, last);
+    }
+    // right block: own columns j-LH .. R-1, descending
+    if constexpr (JR <= R - 1) {
+        Col<M> Q = suf;                       // V[R-LH .. R-1]
+#pragma unroll
+        for (int j = R - 1; j >= JR; j--) {
+            const int a = j - LH;
+            if (a < R - LH) col_add<M>(Q, V[a]);
+            Col<M> S = Q;
+            const int mr = j + RH - (R - 1);
+            if (mr > 0) col_add<M>(S, Rx[mr]);
+            emit(j, S);
+        }
+    }
+}
+
+// Window sums of one output row, whichever form fits the window width.
+template <int M, int R, int KW, class Emit>
+__device__ __forceinline__ void hsum_row(const Col<M> (&V)[R], Emit&& emit)
+{
+    if constexpr (hsum_one_hop<M, R, KW>())
+        hsum_onehop<M, R, KW>(V, emit);
+    else
+        hslide<M, R, KW>(V, emit);
+}
+
+typedef uint32_t v4u32 __attribute__((ext_vector_type(4)));
+typedef uint32_t v2u32 __attribute__((ext_vector_type(2)));
+
+// NW consecutive 32-bit words at byte offset `off` of a raw buffer.
+template <int NW>
+__device__ __forceinline__ void buf_load_words(__amdgpu_buffer_rsrc_t rs, uint32_t off, uint32_t* w)
+{
+    if constexpr (NW == 1) {
+        w[0] = __builtin_amdgcn_raw_buffer_load_b32(rs, off, 0, 0);
+    } else if constexpr (NW == 2) {
+        const v2u32 v = __builtin_amdgcn_raw_buffer_load_b64(rs, off, 0, 0);
+        w[0] = v.x; w[1] = v.y;
+    } else {
+        static_assert(NW % 4 == 0, "1, 2 or a multiple of 4 words");
+#pragma unroll
+        for (int i = 0; i < NW; i += 4) {
+            const v4u32 v = __builtin_amdgcn_raw_buffer_load_b128(rs, off + 4u * i, 0, 0);
+            w[i] = v.x; w[i + 1] = v.y; w[i + 2] = v.z; w[i + 3] = v.w;
+        }
+    }
+}
+
+
+// Returns v unchanged but hides it from the optimiser, so that values derived
+// from per-lane constants are recomputed where they are used instead of being
+// hoisted out of the row loop (where they would only occupy registers).
+template <class T> __device__ __forceinline__ T opaque(T v)
+{
+    asm volatile("" : "+v"(v));
+    return v;
+}
+
+template <bool B> struct BoolTag {
+    static constexpr bool value = B;
+};
+
+// Correctly rounded float32 of N / sqrt(q), q = Vx Vy, from exact integers
+// (q > 0): FP64 rsqrt estimate and one Newton step (relative error < 2^-38);
+// `amb` is set when the 29 discarded mantissa bits lie within 2^15 of the
+// rounding midpoint, where only the exact decision is trustworthy.
+__device__ __forceinline__ float rn32_fast(double N, double q, bool& amb)
+{
+    const double r = __builtin_amdgcn_rsq(q);
+    const double t = q * r;
+    const double e = __builtin_fma(-t, r, 1.0);        // 1 - q r^2
+    const double a0 = N * r;
+    const double a = __builtin_fma(0.5 * a0, e, a0);   // N r (1 + e/2)
+    const uint32_t lo = (uint32_t)__double_as_longlong(a) & 0x1FFFFFFFu;
+    amb = (lo - (0x10000000u - (1u << 15))) <= (2u << 15);
+    return (float)a;
+}
+
 // One tile of the fused 2-D correlation (see the file comment).  `smem` is
-// this wave's LDS region of fast2d_lds_per_wave(M, R, kh) bytes.
+// this wave's LDS region of fast2d_lds_per_wave(M, R, kh) bytes.  `tile` is
+// wave-uniform.
 template <int M, int R, int KW, bool VEC>
 __device__ __forceinline__ void tile2d(const P2DF& g, const int tile, char* smem)
 {
     using T = typename Tr<M>::T;
     constexpr int LH = KW / 2;
-    constexpr int RH = KW - 1 - LH;
     constexpr int D = fast2d_depth<M, R>();
     constexpr int NW = Run<T, R>::NW;
     constexpr bool kFloat = (M == MODE_F64);
+    constexpr uint32_t kFull = (1u << R) - 1u;
     const int lane = threadIdx.x & (kWave - 1);
 
     // ---- tile geometry (wave-uniform) ----
@@ -283,6 +459,8 @@ __device__ __forceinline__ void tile2d(const P2DF& g, const int tile, char* smem
     const int rlo = max(i0, 0);
     const int rhi = min(i0 + nrows - 1, H - 1);
     const bool rows_inside = (i0 >= 0) && (i0 + nrows - 1 <= H - 1);
+    // every output column of the tile has its whole window inside [0, W)
+    const bool cols_inside = (E >= 0) && ((q0 + qw - 1) * g.sw + g.ow + KW - 1 <= W - 1);
     // Alternate the march direction between vertically adjacent tiles: both
     // tiles that share a halo band then read it at the same moment (both at
     // the start or both at the end of their march), so one of them hits L2.
@@ -303,11 +481,13 @@ __device__ __forceinline__ void tile2d(const P2DF& g, const int tile, char* smem
         colok |= ok ? (1u << j) : 0u;
         cidx[j] = ok ? c : (c < 0 ? 0 : W - 1);
     }
-    // VEC: a lane's run is entirely inside or outside [0, W)
-    const uint32_t lane_boff = VEC ? (uint32_t)((colok & 1u) ? c0 : 0) * (uint32_t)sizeof(T) : 0u;
+    // VEC (W a multiple of R): a lane's run is entirely inside or outside [0, W)
+    // per column: byte offset of its output in the output row (kOffNone when
+    // the column is not an output of this tile), clipped column count
+    // (packed 8 bits each), FILL-border bit
     uint32_t omask = 0, fillb = 0;
-    int qj[R];
-    double ncol[R];
+    uint32_t qoff[R];
+    uint32_t ncolp[(R + 3) / 4] = {};
 #pragma unroll
     for (int j = 0; j < R; j++) {
         const int qs = c0 + j - g.ow - LH;          // = q*sw when column c0+j is a centre
@@ -316,19 +496,24 @@ __device__ __forceinline__ void tile2d(const P2DF& g, const int tile, char* smem
             q = (g.sw == 1) ? qs : qs / g.sw;
             if (q * g.sw != qs) q = -1;
         }
-        omask |= (q >= q0 && q < q0 + qw) ? (1u << j) : 0u;
-        qj[j] = q;
+        const bool out = q >= q0 && q < q0 + qw;
+        omask |= out ? (1u << j) : 0u;
+        qoff[j] = out ? (uint32_t)q * 4u : kOffNone;
         const int clo = q * g.sw + g.ow, chi = clo + KW - 1;
         fillb |= (fill && (clo < 0 || chi >= W)) ? (1u << j) : 0u;
-        ncol[j] = (double)(min(chi, W - 1) - max(clo, 0) + 1);
+        ncolp[j / 4] |= (uint32_t)(min(chi, W - 1) - max(clo, 0) + 1) << (8 * (j % 4));
     }
+    // lane-aligned outputs (unit column step, centred windows, every lane
+    // either full or empty): each lane stores its R results as vectors
+    const bool tile_vec = (g.vst & 1) &&
+                          __builtin_amdgcn_ballot_w64(omask != 0u && omask != kFull) == 0;
+    const uint32_t voff = omask ? (uint32_t)c0 * 4u : kOffNone;    // c0 = first output column
+    const uint32_t vfoff = omask ? (uint32_t)c0 : kOffNone;
 
-    // ---- per-wave LDS: ring of the last k_h raw rows, zeroed, and a stash ----
-    char* wbase = smem;
-    uint32_t* ringx = (uint32_t*)wbase;                         // [kh][64][NW]
+    // ---- per-wave LDS: ring of the last k_h raw rows, zeroed ----
+    uint32_t* ringx = (uint32_t*)smem;                          // [kh][64][NW]
     uint32_t* ringy = ringx + kh * kWave * NW;
     int* ringm = (int*)(ringy + kh * kWave * NW);                // [kh][64] (float input)
-    double* stash = (double*)(wbase + ((fast2d_ring_bytes(M, R, kh) + 15) & ~15));
     for (int s = 0; s < kh; s++) {
 #pragma unroll
         for (int i = 0; i < NW; i++) {
@@ -345,15 +530,23 @@ __device__ __forceinline__ void tile2d(const P2DF& g, const int tile, char* smem
 
     const char* __restrict__ Xb = (const char*)g.x;
     const char* __restrict__ Yb = (const char*)g.y;
+    // VEC: raw buffer loads over one input row; rows outside the array have a
+    // zero record count and lanes outside it an out-of-range offset, so both
+    // read zeros
+    const uint32_t lane_vo = (colok & 1u) ? (uint32_t)c0 * (uint32_t)sizeof(T) : kOffNone;
     auto issue = [&](int r, Run<T, R>& out) {
-        r = r < rlo ? rlo : (r > rhi ? rhi : r);
         if constexpr (VEC) {
-            const size_t rb = (size_t)r * (size_t)W * sizeof(T);
-            const T* px = (const T*)__builtin_assume_aligned(Xb + rb + lane_boff, sizeof(T) * R);
-            const T* py = (const T*)__builtin_assume_aligned(Yb + rb + lane_boff, sizeof(T) * R);
-            __builtin_memcpy(out.x, px, sizeof(T) * R);
-            __builtin_memcpy(out.y, py, sizeof(T) * R);
+            const bool rin = r >= 0 && r < H;
+            const size_t rb = (size_t)(rin ? r : 0) * (size_t)W * sizeof(T);
+            const int nrec = rin ? W * (int)sizeof(T) : 0;
+            const __amdgpu_buffer_rsrc_t bx =
+                __builtin_amdgcn_make_buffer_rsrc((void*)(Xb + rb), (short)0, nrec, kBufWord3);
+            const __amdgpu_buffer_rsrc_t by =
+                __builtin_amdgcn_make_buffer_rsrc((void*)(Yb + rb), (short)0, nrec, kBufWord3);
+            buf_load_words<NW>(bx, lane_vo, out.x);
+            buf_load_words<NW>(by, lane_vo, out.y);
         } else {
+            r = r < rlo ? rlo : (r > rhi ? rhi : r);
             const T* xr = (const T*)g.x + (size_t)r * W;
             const T* yr = (const T*)g.y + (size_t)r * W;
             T vx[R], vy[R];
@@ -364,6 +557,171 @@ __device__ __forceinline__ void tile2d(const P2DF& g, const int tile, char* smem
             __builtin_memcpy(wy, vy, sizeof(T) * R);
 #pragma unroll
             for (int i = 0; i < NW; i++) { out.x[i] = wx[i]; out.y[i] = wy[i]; }
+        }
+    };
+
+    // ---- step 3-4 for output row p: window sums along the row, epilogue,
+    //      store.  IN: the row and every output column of the tile are
+    //      interior (full windows, no border handling). ----
+    auto out_row = [&](int p, auto in_tag) {
+        constexpr bool IN = decltype(in_tag)::value;
+        const int rlo_w = p * g.sh + g.oh, rhi_w = rlo_w + kh - 1;
+        const bool row_b = fill && (rlo_w < 0 || rhi_w >= H);
+        uint32_t fillb_r = 0, ncolp_r[(R + 3) / 4] = {};
+        if constexpr (!IN) {
+            fillb_r = opaque(fillb);
+#pragma unroll
+            for (int i = 0; i < (R + 3) / 4; i++) ncolp_r[i] = opaque(ncolp[i]);
+        }
+        auto ncol_r = [&](int j) -> int { return (int)((ncolp_r[j / 4] >> (8 * (j % 4))) & 0xFFu); };
+        const int rl = max(rlo_w, 0), rh_ = min(rhi_w, H - 1);
+        const double nrow = (double)(rh_ - rl + 1);
+        const double dn_in = (double)(kh * KW);
+        double gx = 0.0, gy = 0.0;   // certification thresholds (float input)
+        if constexpr (kFloat) {
+            const double Mx = (double)fmaxf(hmx, fmaxf(__uint_as_float(dpp_from_left(__float_as_uint(hmx))),
+                                                __uint_as_float(dpp_from_right(__float_as_uint(hmx)))));
+            const double My = (double)fmaxf(hmy, fmaxf(__uint_as_float(dpp_from_left(__float_as_uint(hmy))),
+                                                __uint_as_float(dpp_from_right(__float_as_uint(hmy)))));
+            gx = g.cert_g * Mx * Mx;
+            gy = g.cert_g * My * My;
+        }
+        float cvals[R];
+        uint32_t flw[(R + 3) / 4] = {};   // flag bytes, packed
+        bool any_pend = false;            // some output of this lane needs the rare path
+        const bool force_exact = (g.force & 1) != 0;
+        // Window quantities of output j from its sums: N, Vx, Vy (exact
+        // integers for integer input) and the FILL-border bit.
+        auto nvv = [&](int j, const Col<M>& S, double& N, double& Vx, double& Vy, bool& fb)
+            __attribute__((always_inline)) {
+            double dn;
+            if constexpr (IN) {
+                dn = dn_in;
+                fb = false;
+            } else {
+                dn = nrow * (double)ncol_r(j);
+                fb = row_b || ((fillb_r >> j) & 1u);
+            }
+            if constexpr (kFloat) {
+                N = __builtin_fma(dn, S.xy, -(S.x * S.y));
+                Vx = __builtin_fma(dn, S.xx, -(S.x * S.x));
+                Vy = __builtin_fma(dn, S.yy, -(S.y * S.y));
+            } else {
+                const double sx = (double)S.x, sy = (double)S.y;
+                N = __builtin_fma(0.5 * dn, (double)S.xy2, -(sx * sy));
+                Vx = __builtin_fma(dn, (double)S.xx, -(sx * sx));
+                Vy = __builtin_fma(dn, (double)S.yy, -(sy * sy));
+            }
+        };
+        hsum_row<M, R, KW>(V, [&](int j, const Col<M>& S) __attribute__((always_inline)) {
+            double N, Vx, Vy;
+            bool fb;
+            nvv(j, S, N, Vx, Vy, fb);
+            const double q = Vx * Vy;
+            float cv;
+            bool bad, pend;
+            if constexpr (kFloat) {
+                const bool cert = (Vx > gx) && (Vy > gy);
+                // FP64 rsqrt estimate and one Newton step
+                const double r = __builtin_amdgcn_rsq(q);
+                const double e = __builtin_fma(-(q * r), r, 1.0);
+                const double a0 = N * r;
+                cv = clamp_unit(__builtin_fma(0.5 * a0, e, a0));
+                bad = fb || (S.miss > 0);
+                pend = !bad && (!cert || force_exact);
+                if (has_flags) {
+                    const uint32_t fl = fb ? FL_BORDER : (S.miss > 0 ? FL_MISSING : 0);
+                    flw[j / 4] |= fl << (8 * (j % 4));
+                }
+            } else {
+                bool amb;
+                cv = rn32_fast(N, q, amb);
+                // Vx, Vy >= 0 are exact integers: a zero product is a zero variance
+                bad = fb || (q == 0.0);
+                pend = !bad && (amb || force_exact);
+                if (has_flags) {
+                    const uint32_t fl = fb ? FL_BORDER
+                                           : ((Vx == 0.0 ? FL_ZVAR_X : 0u) | (Vy == 0.0 ? FL_ZVAR_Y : 0u));
+                    flw[j / 4] |= fl << (8 * (j % 4));
+                }
+            }
+            cvals[j] = bad ? g.invalid : cv;
+            any_pend = any_pend || (pend && ((omask >> j) & 1u));
+            // one output at a time: interleaving the R epilogues buys no
+            // latency hiding worth the registers it costs
+            __builtin_amdgcn_sched_barrier(0);
+        });
+        // rare path: exact decisions (integer input) / two-pass recomputation
+        // (float input) for the outputs whose fast result is not certified.
+        // The window sums are recomputed (the slide is deterministic), so the
+        // common path keeps nothing for them.
+        if (__builtin_amdgcn_ballot_w64(any_pend)) {
+            hsum_row<M, R, KW>(V, [&](int j, const Col<M>& S) __attribute__((always_inline)) {
+                double N, Vx, Vy;
+                bool fb;
+                nvv(j, S, N, Vx, Vy, fb);
+                const double q = Vx * Vy;
+                if constexpr (kFloat) {
+                    const bool pend = !fb && S.miss <= 0 &&
+                                      (!((Vx > gx) && (Vy > gy)) || force_exact) &&
+                                      ((omask >> j) & 1u);
+                    if (pend) {
+                        const int clo = (int)(opaque(qoff[j]) >> 2) * g.sw + g.ow;
+                        const int64_t cl = max(clo, 0);
+                        const int64_t ch = min(clo + KW - 1, W - 1);
+                        float cvr = 0.f;
+                        const uint8_t f2 = twopass_window((const float*)g.x, (const float*)g.y,
+                                                          (int64_t)W, 1, rl, rh_, cl, ch, 0, 0, &cvr);
+                        flw[j / 4] = (flw[j / 4] & ~(0xFFu << (8 * (j % 4)))) |
+                                     ((uint32_t)f2 << (8 * (j % 4)));
+                        cvals[j] = f2 ? g.invalid : cvr;
+                    }
+                } else {
+                    bool amb;
+                    (void)rn32_fast(N, q, amb);
+                    const bool pend = !fb && q != 0.0 && (amb || force_exact) && ((omask >> j) & 1u);
+                    if (pend) {
+                        const double aN = __builtin_fabs(N);
+                        // any estimate far inside half an ulp selects the right bucket
+                        const float f = rn32_exact_decide(aN, Vx, Vy, aN / __builtin_sqrt(q));
+                        cvals[j] = N < 0.0 ? -f : f;
+                    }
+                }
+            });
+        }
+        // ---- stores: buffer stores over the output row; columns that are
+        //      not outputs of this tile carry an out-of-range offset ----
+        const size_t orow = (size_t)p * (size_t)g.OW;
+        const __amdgpu_buffer_rsrc_t rc =
+            __builtin_amdgcn_make_buffer_rsrc(g.c + orow, (short)0, g.OW * 4, kBufWord3);
+        if (tile_vec) {
+#pragma unroll
+            for (int j = 0; j < R; j += 4) {
+                v4u32 v = {__float_as_uint(cvals[j]), __float_as_uint(cvals[j + 1]),
+                           __float_as_uint(cvals[j + 2]), __float_as_uint(cvals[j + 3])};
+                __builtin_amdgcn_raw_buffer_store_b128(v, rc, voff + 4u * j, 0, 0);
+            }
+        } else {
+#pragma unroll
+            for (int j = 0; j < R; j++)
+                __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(cvals[j]), rc, qoff[j], 0, 0);
+        }
+        if (has_flags) {
+            const __amdgpu_buffer_rsrc_t rf =
+                __builtin_amdgcn_make_buffer_rsrc(g.flags + orow, (short)0, g.OW, kBufWord3);
+            if (tile_vec && (g.vst & 2)) {
+#pragma unroll
+                for (int i = 0; i < R / 4; i++)
+                    __builtin_amdgcn_raw_buffer_store_b32(flw[i], rf, vfoff + 4u * i, 0, 0);
+            } else {
+#pragma unroll
+                for (int j = 0; j < R; j++) {
+                    const uint32_t qo = opaque(qoff[j]);
+                    __builtin_amdgcn_raw_buffer_store_b8(
+                        (uint8_t)(flw[j / 4] >> (8 * (j % 4))), rf,
+                        qo == kOffNone ? kOffNone : qo >> 2, 0, 0);
+                }
+            }
         }
     };
 
@@ -386,11 +744,11 @@ __device__ __forceinline__ void tile2d(const P2DF& g, const int tile, char* smem
             uint32_t wx[NW], wy[NW];
 #pragma unroll
             for (int i = 0; i < NW; i++) { wx[i] = pf[u].x[i]; wy[i] = pf[u].y[i]; }
-            if (!rows_inside && (row < rlo || row > rhi)) {
+            if (!VEC && !rows_inside && (row < rlo || row > rhi)) {
 #pragma unroll
                 for (int i = 0; i < NW; i++) { wx[i] = 0u; wy[i] = 0u; }
             }
-            if (edge) {
+            if (!VEC && edge) {
                 T vx[R], vy[R];
                 __builtin_memcpy(vx, wx, sizeof(T) * R);
                 __builtin_memcpy(vy, wy, sizeof(T) * R);
@@ -451,145 +809,39 @@ __device__ __forceinline__ void tile2d(const P2DF& g, const int tile, char* smem
             }
             if (li != next_ready) continue;
             next_ready += g.sh;
-
-            // ---- step 3: window sums along the row ----
-            Col<M> S, keepL[R > 1 ? R - 1 : 1], keepR[R > 1 ? R - 1 : 1];
-            halo_window<M, R, KW>(V, S, keepL, keepR);
-            double gx = 0.0, gy = 0.0;   // certification thresholds (float input)
-            if constexpr (kFloat) {
-                const double Mx = (double)fmaxf(hmx, fmaxf(__uint_as_float(dpp_from_left(__float_as_uint(hmx))),
-                                                    __uint_as_float(dpp_from_right(__float_as_uint(hmx)))));
-                const double My = (double)fmaxf(hmy, fmaxf(__uint_as_float(dpp_from_left(__float_as_uint(hmy))),
-                                                    __uint_as_float(dpp_from_right(__float_as_uint(hmy)))));
-                gx = g.cert_g * Mx * Mx;
-                gy = g.cert_g * My * My;
-            }
-            // wave-uniform row quantities
-            const int rlo_w = p * g.sh + g.oh, rhi_w = rlo_w + kh - 1;
-            const bool row_b = fill && (rlo_w < 0 || rhi_w >= H);
-            const int rl = max(rlo_w, 0), rh_ = min(rhi_w, H - 1);
-            const double nrow = (double)(rh_ - rl + 1);
-            const size_t orow = (size_t)p * (size_t)g.OW;
-            float* __restrict__ crow = g.c + orow;
-
-            uint32_t pending = 0;
-            float cvals[R];
-            uint8_t fls[R];
-#pragma unroll
-            for (int j = 0; j < R; j++) {
-                if (j > 0) {
-                    const int ca = j + RH, cs = j - 1 - LH;
-                    const Col<M>& va = ca < R ? V[ca] : keepR[ca - RH - 1];
-                    const Col<M>& vs = cs < 0 ? keepL[cs + LH] : V[cs];
-                    col_add<M>(S, va);
-                    col_sub<M>(S, vs);
-                }
-                // ---- step 4: epilogue (branch-free; rare cases deferred) ----
-                const bool fb = row_b || ((fillb >> j) & 1u);
-                const double dn = nrow * ncol[j];
-                uint8_t fl = 0;
-                float cv;
-                if constexpr (kFloat) {
-                    const double N = __builtin_fma(dn, S.xy, -(S.x * S.y));
-                    const double Vx = __builtin_fma(dn, S.xx, -(S.x * S.x));
-                    const double Vy = __builtin_fma(dn, S.yy, -(S.y * S.y));
-                    const bool cert = (Vx > gx) && (Vy > gy);
-                    // FP64 rsqrt estimate (relative error ~2^-23) and one Newton step
-                    const double q = Vx * Vy;
-                    double r = __builtin_amdgcn_rsq(q);
-                    const double e = __builtin_fma(q * r, r, -1.0);
-                    r = r * __builtin_fma(e, -0.5, 1.0);
-                    cv = clamp_unit(N * r);
-                    const bool bad = fb || (S.miss > 0);
-                    if (bad) {
-                        fl = fb ? FL_BORDER : FL_MISSING;
-                        cv = g.invalid;
-                    }
-                    const bool pend = !bad && (!cert || (g.force & 1));
-                    pending |= pend ? (1u << j) : 0u;
-                } else {
-                    const double sx = (double)S.x, sy = (double)S.y;
-                    const double N = __builtin_fma(0.5 * dn, (double)S.xy2, -(sx * sy));
-                    const double Vx = __builtin_fma(dn, (double)S.xx, -(sx * sx));
-                    const double Vy = __builtin_fma(dn, (double)S.yy, -(sy * sy));
-                    // certified RN32 estimate: v_rsq_f64 (relative error well
-                    // below 2^-20) and one Newton step leave < 2^-38; outputs
-                    // whose 29 discarded mantissa bits lie within 2^15 of the
-                    // midpoint pattern take the exact decision
-                    const double q = Vx * Vy;
-                    double r = __builtin_amdgcn_rsq(q);
-                    const double e = __builtin_fma(q * r, r, -1.0);
-                    r = r * __builtin_fma(e, -0.5, 1.0);
-                    const double a = __builtin_fabs(N) * r;
-                    const uint32_t t = (uint32_t)__double_as_longlong(a) & 0x1FFFFFFFu;
-                    const bool amb = (t - (0x10000000u - (1u << 15))) <= (2u << 15);
-                    const float f = (float)a;
-                    cv = (N < 0.0) ? -f : f;
-                    const bool bad = fb || (q == 0.0);   // Vx, Vy >= 0 are exact integers
-                    if (bad) {
-                        fl = fb ? FL_BORDER : (uint8_t)((Vx == 0.0 ? FL_ZVAR_X : 0) | (Vy == 0.0 ? FL_ZVAR_Y : 0));
-                        cv = g.invalid;
-                    }
-                    const bool pend = !bad && (amb || (g.force & 1));
-                    pending |= pend ? (1u << j) : 0u;
-                    if (pend) {
-                        double* st = stash + (size_t)(j * kWave + lane) * 3;
-                        st[0] = N; st[1] = Vx; st[2] = Vy;
-                    }
-                }
-                cvals[j] = cv;
-                fls[j] = fl;
-            }
-            // rare path: exact decisions / two-pass recomputation
-            if (pending) {
-                for (int j = 0; j < R; j++) {
-                    if (!((pending >> j) & 1u)) continue;
-                    if constexpr (kFloat) {
-                        const int64_t clo = (int64_t)qj[j] * g.sw + g.ow;
-                        const int64_t cl = clo < 0 ? 0 : clo;
-                        const int64_t ch = clo + KW - 1 > W - 1 ? W - 1 : clo + KW - 1;
-                        float cvr = 0.f;
-                        const uint8_t f2 = twopass_window((const float*)g.x, (const float*)g.y,
-                                                          (int64_t)W, 1, rl, rh_, cl, ch, 0, 0, &cvr);
-#pragma unroll
-                        for (int jj = 0; jj < R; jj++)
-                            if (jj == j) { fls[jj] = f2; cvals[jj] = f2 ? g.invalid : cvr; }
-                    } else {
-                        const double* st = stash + (size_t)(j * kWave + lane) * 3;
-                        const double N = st[0];
-                        // any estimate far inside half an ulp selects the right bucket
-                        const double a = __builtin_fabs(N) / __builtin_sqrt(st[1] * st[2]);
-                        float f = rn32_exact_decide(__builtin_fabs(N), st[1], st[2], a);
-                        f = N < 0.0 ? -f : f;
-#pragma unroll
-                        for (int jj = 0; jj < R; jj++)
-                            if (jj == j) cvals[jj] = f;
-                    }
-                }
-            }
-#pragma unroll
-            for (int j = 0; j < R; j++) {
-                if ((omask >> j) & 1u) {
-                    crow[(uint32_t)qj[j]] = cvals[j];
-                    if (has_flags) g.flags[orow + (uint32_t)qj[j]] = fls[j];
-                }
-            }
+            const int rw = p * g.sh + g.oh;
+            if (cols_inside && rw >= 0 && rw + kh - 1 <= H - 1)
+                out_row(p, BoolTag<true>{});
+            else
+                out_row(p, BoolTag<false>{});
             p += pstep;
         }
     }
 }
 
-// Occupancy target: three waves per SIMD for the integer kernels with R = 4
-// (their register and LDS footprints allow it), two otherwise.
-template <int M, int R> constexpr int fast2d_min_waves() { return (M != MODE_F64 && R == 4) ? 3 : 2; }
+// Occupancy target (waves per SIMD the register allocation must allow):
+// three for the integer kernels with R = 4, two otherwise.  The macros let a
+// variant build try other targets.
+#ifndef SWC_FAST2D_WAVES_INT4
+#define SWC_FAST2D_WAVES_INT4 3
+#endif
+#ifndef SWC_FAST2D_WAVES_OTHER
+#define SWC_FAST2D_WAVES_OTHER 2
+#endif
+template <int M, int R> constexpr int fast2d_min_waves()
+{
+    return (M != MODE_F64 && R == 4) ? SWC_FAST2D_WAVES_INT4 : SWC_FAST2D_WAVES_OTHER;
+}
 
 template <int M, int R, int KW, bool VEC>
 __global__ void __launch_bounds__(256)
 __attribute__((amdgpu_waves_per_eu(fast2d_min_waves<M, R>(), 8))) corr2d_fast_kernel(P2DF g)
 {
     extern __shared__ __attribute__((aligned(16))) char smem[];
-    const int wv = threadIdx.x / kWave;
     const int wpb = blockDim.x / kWave;
+    // the wave index is uniform across the wave; say so, so that all tile
+    // geometry lives in scalar registers
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
     const int tile = xcd_remap(blockIdx.x, gridDim.x) * wpb + wv;
     if (tile >= g.n_tiles) return;
     tile2d<M, R, KW, VEC>(g, tile, smem + (size_t)wv * fast2d_lds_per_wave(M, R, g.kh));

@@ -318,7 +318,7 @@ template <int M, int R, int KW, int TY, bool VEC>
 __global__ void __launch_bounds__(256)
 __attribute__((amdgpu_waves_per_eu(2, 8))) corr3d_kernel(P3D g)
 {
-    const int wv = threadIdx.x / kWave;
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);   // wave-uniform
     const int wpb = blockDim.x / kWave;
     const int tile = xcd_remap(blockIdx.x, gridDim.x) * wpb + wv;
     if (tile >= g.n_tiles) return;
