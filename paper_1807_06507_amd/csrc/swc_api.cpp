@@ -135,7 +135,7 @@ LaunchCfg default_cfg(const swc_problem* p)
     if (p->ndim == 2) {
         L.R = 4;
         L.TH = 0;     // tile height chosen per launch from the resident-wave count
-        L.wpb = 1;
+        L.wpb = 4;
         if (p->window[1] > 4 * 64 - 3) L.R = 8;
     } else if (p->ndim == 1) {
         L.R = 8;

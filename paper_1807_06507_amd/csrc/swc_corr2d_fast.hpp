@@ -214,9 +214,20 @@ __device__ __forceinline__ void issue_run(const T* __restrict__ xl, const T* __r
     }
 }
 
+#ifndef SWC_FAST2D_EPI_GROUP
+#define SWC_FAST2D_EPI_GROUP 1
+#endif
+
+// Rows prefetched ahead into registers.  One is enough for the integer
+// kernels, which keep three waves per SIMD to cover the latency; the float
+// kernel (two waves) looks further ahead.  A variant build may override it.
 template <int M, int R> constexpr int fast2d_depth()
 {
-    return 4;
+#ifdef SWC_FAST2D_DEPTH
+    return SWC_FAST2D_DEPTH;
+#else
+    return M == MODE_F64 ? 2 : 1;
+#endif
 }
 
 // ---- halo exchange + first window sum ------------------------------------
@@ -563,7 +574,7 @@ __device__ __forceinline__ void tile2d(const P2DF& g, const int tile, char* smem
     // ---- step 3-4 for output row p: window sums along the row, epilogue,
     //      store.  IN: the row and every output column of the tile are
     //      interior (full windows, no border handling). ----
-    auto out_row = [&](int p, auto in_tag) {
+    auto out_row = [&](int p, auto in_tag, float (&cvals)[R], uint32_t (&flw)[(R + 3) / 4]) {
         constexpr bool IN = decltype(in_tag)::value;
         const int rlo_w = p * g.sh + g.oh, rhi_w = rlo_w + kh - 1;
         const bool row_b = fill && (rlo_w < 0 || rhi_w >= H);
@@ -586,8 +597,6 @@ __device__ __forceinline__ void tile2d(const P2DF& g, const int tile, char* smem
             gx = g.cert_g * Mx * Mx;
             gy = g.cert_g * My * My;
         }
-        float cvals[R];
-        uint32_t flw[(R + 3) / 4] = {};   // flag bytes, packed
         bool any_pend = false;            // some output of this lane needs the rare path
         const bool force_exact = (g.force & 1) != 0;
         // Window quantities of output j from its sums: N, Vx, Vy (exact
@@ -621,14 +630,14 @@ __device__ __forceinline__ void tile2d(const P2DF& g, const int tile, char* smem
             float cv;
             bool bad, pend;
             if constexpr (kFloat) {
-                const bool cert = (Vx > gx) && (Vy > gy);
+                const bool cert = (Vx > gx) & (Vy > gy);
                 // FP64 rsqrt estimate and one Newton step
                 const double r = __builtin_amdgcn_rsq(q);
                 const double e = __builtin_fma(-(q * r), r, 1.0);
                 const double a0 = N * r;
                 cv = clamp_unit(__builtin_fma(0.5 * a0, e, a0));
-                bad = fb || (S.miss > 0);
-                pend = !bad && (!cert || force_exact);
+                bad = fb | (S.miss > 0);
+                pend = (!bad) & ((!cert) | force_exact);
                 if (has_flags) {
                     const uint32_t fl = fb ? FL_BORDER : (S.miss > 0 ? FL_MISSING : 0);
                     flw[j / 4] |= fl << (8 * (j % 4));
@@ -637,19 +646,24 @@ __device__ __forceinline__ void tile2d(const P2DF& g, const int tile, char* smem
                 bool amb;
                 cv = rn32_fast(N, q, amb);
                 // Vx, Vy >= 0 are exact integers: a zero product is a zero variance
-                bad = fb || (q == 0.0);
-                pend = !bad && (amb || force_exact);
+                bad = fb | (q == 0.0);
+                pend = (!bad) & (amb | force_exact);
                 if (has_flags) {
                     const uint32_t fl = fb ? FL_BORDER
                                            : ((Vx == 0.0 ? FL_ZVAR_X : 0u) | (Vy == 0.0 ? FL_ZVAR_Y : 0u));
                     flw[j / 4] |= fl << (8 * (j % 4));
                 }
             }
-            cvals[j] = bad ? g.invalid : cv;
-            any_pend = any_pend || (pend && ((omask >> j) & 1u));
-            // one output at a time: interleaving the R epilogues buys no
-            // latency hiding worth the registers it costs
-            __builtin_amdgcn_sched_barrier(0);
+            // opaque: keep the estimate unconditional (straight-line code
+            // instead of a branch around it for the rare invalid lanes)
+            const float cvo = opaque(cv);
+            cvals[j] = bad ? g.invalid : cvo;
+            any_pend = any_pend | (pend & (((omask >> j) & 1u) != 0));
+            // epilogues are scheduled in groups of SWC_FAST2D_EPI_GROUP
+            // outputs: interleaving more of them hides more latency but
+            // costs registers
+            if ((j % SWC_FAST2D_EPI_GROUP) == SWC_FAST2D_EPI_GROUP - 1)
+                __builtin_amdgcn_sched_barrier(0);
         });
         // rare path: exact decisions (integer input) / two-pass recomputation
         // (float input) for the outputs whose fast result is not certified.
@@ -689,135 +703,191 @@ __device__ __forceinline__ void tile2d(const P2DF& g, const int tile, char* smem
                 }
             });
         }
-        // ---- stores: buffer stores over the output row; columns that are
-        //      not outputs of this tile carry an out-of-range offset ----
-        const size_t orow = (size_t)p * (size_t)g.OW;
+    };
+
+    // ---- stores of one step: buffer stores over an output row; columns
+    //      that are not outputs of this tile carry an out-of-range offset,
+    //      and a step without an output row (or a launch without flags)
+    //      stores through a zero-length record.  Every step issues the same
+    //      stores, so the loads still in flight can be counted exactly when
+    //      the next row is waited for (stores share that counter). ----
+    auto store_row = [&](bool emit, int64_t orow_p, auto svec_tag, const float (&cvals)[R],
+                         const uint32_t (&flw)[(R + 3) / 4]) {
+        constexpr bool SVEC = decltype(svec_tag)::value;
+        const int64_t orow = emit ? orow_p : 0;
         const __amdgpu_buffer_rsrc_t rc =
-            __builtin_amdgcn_make_buffer_rsrc(g.c + orow, (short)0, g.OW * 4, kBufWord3);
-        if (tile_vec) {
+            __builtin_amdgcn_make_buffer_rsrc(g.c + orow, (short)0, emit ? g.OW * 4 : 0, kBufWord3);
+        const __amdgpu_buffer_rsrc_t rf = __builtin_amdgcn_make_buffer_rsrc(
+            has_flags ? (void*)(g.flags + orow) : (void*)g.c, (short)0,
+            (emit && has_flags) ? g.OW : 0, kBufWord3);
+        if constexpr (SVEC) {
 #pragma unroll
             for (int j = 0; j < R; j += 4) {
                 v4u32 v = {__float_as_uint(cvals[j]), __float_as_uint(cvals[j + 1]),
                            __float_as_uint(cvals[j + 2]), __float_as_uint(cvals[j + 3])};
                 __builtin_amdgcn_raw_buffer_store_b128(v, rc, voff + 4u * j, 0, 0);
             }
+#pragma unroll
+            for (int i = 0; i < R / 4; i++)
+                __builtin_amdgcn_raw_buffer_store_b32(flw[i], rf, vfoff + 4u * i, 0, 0);
         } else {
 #pragma unroll
             for (int j = 0; j < R; j++)
                 __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(cvals[j]), rc, qoff[j], 0, 0);
-        }
-        if (has_flags) {
-            const __amdgpu_buffer_rsrc_t rf =
-                __builtin_amdgcn_make_buffer_rsrc(g.flags + orow, (short)0, g.OW, kBufWord3);
-            if (tile_vec && (g.vst & 2)) {
 #pragma unroll
-                for (int i = 0; i < R / 4; i++)
-                    __builtin_amdgcn_raw_buffer_store_b32(flw[i], rf, vfoff + 4u * i, 0, 0);
-            } else {
-#pragma unroll
-                for (int j = 0; j < R; j++) {
-                    const uint32_t qo = opaque(qoff[j]);
-                    __builtin_amdgcn_raw_buffer_store_b8(
-                        (uint8_t)(flw[j / 4] >> (8 * (j % 4))), rf,
-                        qo == kOffNone ? kOffNone : qo >> 2, 0, 0);
-                }
+            for (int j = 0; j < R; j++) {
+                const uint32_t qo = opaque(qoff[j]);
+                __builtin_amdgcn_raw_buffer_store_b8((uint8_t)(flw[j / 4] >> (8 * (j % 4))), rf,
+                                                     qo == kOffNone ? kOffNone : qo >> 2, 0, 0);
             }
         }
     };
 
-    Run<T, R> pf[D];
-#pragma unroll
-    for (int u = 0; u < D; u++) issue(up ? i1 - u : i0 + u, pf[u]);
-
-    int slot = 0;
-    int next_ready = kh - 1;
-    int p = up ? p0 + ph - 1 : p0;
-    const int pstep = up ? -1 : 1;
-    const int rstep = up ? -1 : 1;
-    for (int base = 0; base < nrows; base += D) {
-#pragma unroll
-        for (int u = 0; u < D; u++) {
-            const int li = base + u;
-            if (li >= nrows) break;
-            const int row = up ? i1 - li : i0 + li;
-            // ---- current row (zero outside the array) ----
-            uint32_t wx[NW], wy[NW];
-#pragma unroll
-            for (int i = 0; i < NW; i++) { wx[i] = pf[u].x[i]; wy[i] = pf[u].y[i]; }
-            if (!VEC && !rows_inside && (row < rlo || row > rhi)) {
-#pragma unroll
-                for (int i = 0; i < NW; i++) { wx[i] = 0u; wy[i] = 0u; }
+    // Prefetch ring of D rows in registers.  The first pass of the loop
+    // (base = -D) only fills it, so that every load is issued from the same
+    // place in the loop body and the compiler can count the loads still in
+    // flight when it waits for the oldest one.
+    // ---- the march down the tile ----
+    auto march = [&](auto svec_tag) {
+        Run<T, R> pf[D];
+        // rows are issued in order, one per step: keep the next row's index
+        // and byte offset in scalar registers instead of recomputing them
+        const int64_t rowbytes = (int64_t)W * (int64_t)sizeof(T);
+        int r_next = up ? i1 : i0;
+        int64_t off_next = (int64_t)r_next * rowbytes;
+        const int64_t off_step = up ? -rowbytes : rowbytes;
+        auto issue_next = [&](Run<T, R>& out) {
+            if constexpr (VEC) {
+                const bool rin = (unsigned)r_next < (unsigned)H;
+                const int nrec = rin ? (int)rowbytes : 0;
+                const int64_t o = rin ? off_next : 0;
+                const __amdgpu_buffer_rsrc_t bx =
+                    __builtin_amdgcn_make_buffer_rsrc((void*)(Xb + o), (short)0, nrec, kBufWord3);
+                const __amdgpu_buffer_rsrc_t by =
+                    __builtin_amdgcn_make_buffer_rsrc((void*)(Yb + o), (short)0, nrec, kBufWord3);
+                buf_load_words<NW>(bx, lane_vo, out.x);
+                buf_load_words<NW>(by, lane_vo, out.y);
+            } else {
+                issue(r_next, out);
             }
-            if (!VEC && edge) {
-                T vx[R], vy[R];
-                __builtin_memcpy(vx, wx, sizeof(T) * R);
-                __builtin_memcpy(vy, wy, sizeof(T) * R);
+            r_next += up ? -1 : 1;
+            off_next += off_step;
+        };
+        // output rows are emitted in order: element offset of row p
+        int64_t orow = (int64_t)(up ? p0 + ph - 1 : p0) * (int64_t)g.OW;
+        const int64_t orow_step = up ? -(int64_t)g.OW : (int64_t)g.OW;
+        int slot = 0;
+        int next_ready = kh - 1;
+        int p = up ? p0 + ph - 1 : p0;
+        const int pstep = up ? -1 : 1;
+        for (int base = -D; base < nrows; base += D) {
 #pragma unroll
-                for (int j = 0; j < R; j++) {
-                    vx[j] = ((colok >> j) & 1u) ? vx[j] : (T)0;
-                    vy[j] = ((colok >> j) & 1u) ? vy[j] : (T)0;
+            for (int u = 0; u < D; u++) {
+                const int li = base + u;
+                if (li >= nrows) break;
+                const int row = up ? i1 - li : i0 + li;
+                if (li >= 0) {
+                // ---- current row (zero outside the array) ----
+                uint32_t wx[NW], wy[NW];
+#pragma unroll
+                for (int i = 0; i < NW; i++) { wx[i] = pf[u].x[i]; wy[i] = pf[u].y[i]; }
+                if (!VEC && !rows_inside && (row < rlo || row > rhi)) {
+#pragma unroll
+                    for (int i = 0; i < NW; i++) { wx[i] = 0u; wy[i] = 0u; }
                 }
-                __builtin_memcpy(wx, vx, sizeof(T) * R);
-                __builtin_memcpy(wy, vy, sizeof(T) * R);
-            }
-            issue(row + D * rstep, pf[u]);
-            // ---- leaving row from the ring (zeros for the first k_h rows) ----
-            const int bw = (slot * kWave + lane) * NW;
-            uint32_t ox[NW], oy[NW];
+                if (!VEC && edge) {
+                    T vx[R], vy[R];
+                    __builtin_memcpy(vx, wx, sizeof(T) * R);
+                    __builtin_memcpy(vy, wy, sizeof(T) * R);
 #pragma unroll
-            for (int i = 0; i < NW; i++) { ox[i] = ringx[bw + i]; oy[i] = ringy[bw + i]; }
-            int omiss = 0, nmiss = 0;
-            if constexpr (kFloat) omiss = ringm[slot * kWave + lane];
-            T ax[R], ay[R], bx[R], by[R];
-            __builtin_memcpy(ax, wx, sizeof(T) * R);
-            __builtin_memcpy(ay, wy, sizeof(T) * R);
-            __builtin_memcpy(bx, ox, sizeof(T) * R);
-            __builtin_memcpy(by, oy, sizeof(T) * R);
-            if constexpr (kFloat) {
-#pragma unroll
-                for (int j = 0; j < R; j++) {
-                    const bool m = is_missing(ax[j], g.miss_thr) || is_missing(ay[j], g.miss_thr);
-                    ax[j] = m ? 0.f : ax[j];
-                    ay[j] = m ? 0.f : ay[j];
-                    nmiss |= m ? (1 << j) : 0;
-                    hmx = fmaxf(hmx, __builtin_fabsf(ax[j]));
-                    hmy = fmaxf(hmy, __builtin_fabsf(ay[j]));
+                    for (int j = 0; j < R; j++) {
+                        vx[j] = ((colok >> j) & 1u) ? vx[j] : (T)0;
+                        vy[j] = ((colok >> j) & 1u) ? vy[j] : (T)0;
+                    }
+                    __builtin_memcpy(wx, vx, sizeof(T) * R);
+                    __builtin_memcpy(wy, vy, sizeof(T) * R);
                 }
-                __builtin_memcpy(wx, ax, sizeof(T) * R);
-                __builtin_memcpy(wy, ay, sizeof(T) * R);
-                ringm[slot * kWave + lane] = nmiss;
-            }
-            // same lane, same address: the read above returns the old row
+                // ---- leaving row from the ring (zeros for the first k_h rows) ----
+                const int bw = (slot * kWave + lane) * NW;
+                uint32_t ox[NW], oy[NW];
 #pragma unroll
-            for (int i = 0; i < NW; i++) { ringx[bw + i] = wx[i]; ringy[bw + i] = wy[i]; }
-            slot = (slot + 1 == kh) ? 0 : slot + 1;
-            // ---- step 2: running column sums ----
-#pragma unroll
-            for (int j = 0; j < R; j++) {
+                for (int i = 0; i < NW; i++) { ox[i] = ringx[bw + i]; oy[i] = ringy[bw + i]; }
+                int omiss = 0, nmiss = 0;
+                if constexpr (kFloat) omiss = ringm[slot * kWave + lane];
+                T ax[R], ay[R], bx[R], by[R];
+                __builtin_memcpy(ax, wx, sizeof(T) * R);
+                __builtin_memcpy(ay, wy, sizeof(T) * R);
+                __builtin_memcpy(bx, ox, sizeof(T) * R);
+                __builtin_memcpy(by, oy, sizeof(T) * R);
                 if constexpr (kFloat) {
-                    const double x = (double)ax[j], y = (double)ay[j];
-                    const double xo = (double)bx[j], yo = (double)by[j];
-                    V[j].x += x - xo;
-                    V[j].y += y - yo;
-                    V[j].xx = __builtin_fma(x, x, __builtin_fma(-xo, xo, V[j].xx));
-                    V[j].yy = __builtin_fma(y, y, __builtin_fma(-yo, yo, V[j].yy));
-                    V[j].xy = __builtin_fma(x, y, __builtin_fma(-xo, yo, V[j].xy));
-                    V[j].miss += ((nmiss >> j) & 1) - ((omiss >> j) & 1);
-                } else {
-                    col_update_int<M>(V[j], (int)ax[j], (int)ay[j], (int)bx[j], (int)by[j]);
+#pragma unroll
+                    for (int j = 0; j < R; j++) {
+                        const bool m = is_missing(ax[j], g.miss_thr) || is_missing(ay[j], g.miss_thr);
+                        ax[j] = m ? 0.f : ax[j];
+                        ay[j] = m ? 0.f : ay[j];
+                        nmiss |= m ? (1 << j) : 0;
+                        hmx = fmaxf(hmx, __builtin_fabsf(ax[j]));
+                        hmy = fmaxf(hmy, __builtin_fabsf(ay[j]));
+                    }
+                    __builtin_memcpy(wx, ax, sizeof(T) * R);
+                    __builtin_memcpy(wy, ay, sizeof(T) * R);
+                    ringm[slot * kWave + lane] = nmiss;
+                }
+                // same lane, same address: the read above returns the old row
+#pragma unroll
+                for (int i = 0; i < NW; i++) { ringx[bw + i] = wx[i]; ringy[bw + i] = wy[i]; }
+                slot = (slot + 1 == kh) ? 0 : slot + 1;
+                // ---- step 2: running column sums ----
+#pragma unroll
+                for (int j = 0; j < R; j++) {
+                    if constexpr (kFloat) {
+                        const double x = (double)ax[j], y = (double)ay[j];
+                        const double xo = (double)bx[j], yo = (double)by[j];
+                        V[j].x += x - xo;
+                        V[j].y += y - yo;
+                        V[j].xx = __builtin_fma(x, x, __builtin_fma(-xo, xo, V[j].xx));
+                        V[j].yy = __builtin_fma(y, y, __builtin_fma(-yo, yo, V[j].yy));
+                        V[j].xy = __builtin_fma(x, y, __builtin_fma(-xo, yo, V[j].xy));
+                        V[j].miss += ((nmiss >> j) & 1) - ((omiss >> j) & 1);
+                    } else {
+                        col_update_int<M>(V[j], (int)ax[j], (int)ay[j], (int)bx[j], (int)by[j]);
+                    }
+                }
+                }
+                // refill this prefetch slot only now: its registers are free, and
+                // the rows in the other slots stay in flight
+                issue_next(pf[u]);
+                const bool emit = li >= 0 && li == next_ready;
+                float cvals[R];
+                uint32_t flw[(R + 3) / 4];
+#pragma unroll
+                for (int j = 0; j < R; j++) cvals[j] = 0.f;
+#pragma unroll
+                for (int i = 0; i < (R + 3) / 4; i++) flw[i] = 0u;
+                if (emit) {
+                    next_ready += g.sh;
+                    const int rw = p * g.sh + g.oh;
+                    if (cols_inside && rw >= 0 && rw + kh - 1 <= H - 1)
+                        out_row(p, BoolTag<true>{}, cvals, flw);
+                    else
+                        out_row(p, BoolTag<false>{}, cvals, flw);
+                }
+                store_row(emit, orow, svec_tag, cvals, flw);
+                if (emit) {
+                    p += pstep;
+                    orow += orow_step;
                 }
             }
-            if (li != next_ready) continue;
-            next_ready += g.sh;
-            const int rw = p * g.sh + g.oh;
-            if (cols_inside && rw >= 0 && rw + kh - 1 <= H - 1)
-                out_row(p, BoolTag<true>{});
-            else
-                out_row(p, BoolTag<false>{});
-            p += pstep;
         }
-    }
+    };
+    // whole-vector stores for the tile (every output lane full, flags
+    // either absent or aligned as well)
+    if (tile_vec && (!has_flags || (g.vst & 2)))
+        march(BoolTag<true>{});
+    else
+        march(BoolTag<false>{});
 }
+
 
 // Occupancy target (waves per SIMD the register allocation must allow):
 // three for the integer kernels with R = 4, two otherwise.  The macros let a
