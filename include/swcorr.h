@@ -180,7 +180,10 @@ typedef struct swc_batch_plan swc_batch_plan;
  * arrays x[i], y[i], c[i], flags[i] (flags may be NULL, or contain NULLs)
  * are device pointers kept by the plan.  Allocates and fills the plan's
  * device-side work list (synchronous, not capture-safe).  The plan owns that
- * memory; free it with swc_batch_plan_destroy. */
+ * memory; free it with swc_batch_plan_destroy.  `lp` may be NULL (tuned or
+ * built-in choice); in it, tile_rows = 0 lets the plan pick about four tiles
+ * per persistent wavefront, and waves_per_block = 0 (or a value whose LDS
+ * rings exceed 64 KB per workgroup) the largest of 4, 2, 1 that fits. */
 swc_status swc_batch_plan_create(int32_t n, const swc_problem *p, const void *const *x,
                                  const void *const *y, float *const *c,
                                  uint8_t *const *flags, const swc_launch_params *lp,

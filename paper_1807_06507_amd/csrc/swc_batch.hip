@@ -123,7 +123,7 @@ swc_status swc_batch_plan_create(int32_t n, const swc_problem* p, const void* co
         if (p[i].accum != p[0].accum) return SWC_ERR_ACCUM;
         if (!x[i] || !y[i] || !c[i]) return SWC_ERR_NULL;
     }
-    int TH = 24, wpb = 2, minw = 0;
+    int TH = 0, wpb = 0, minw = 0;   // 0: chosen below
     swc_launch_params tuned;
     if (!(lp && (lp->tile_rows || lp->waves_per_block)) &&
         tune_lookup(p[0].dtype, 2, p[0].accum, 0, &tuned))
@@ -133,12 +133,42 @@ swc_status swc_batch_plan_create(int32_t n, const swc_problem* p, const void* co
         TH = lp->tile_rows;
         wpb = lp->waves_per_block;
         minw = lp->min_waves_per_eu;
-        if (TH < 1 || TH > 4096 || !(wpb == 1 || wpb == 2 || wpb == 4)) return SWC_ERR_PARAM;
+        if (TH < 0 || TH > 4096 || !(wpb == 0 || wpb == 1 || wpb == 2 || wpb == 4))
+            return SWC_ERR_PARAM;
     }
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess) return SWC_ERR_DEVICE;
     int cus = 256;
     hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+
+    // pairs the persistent kernel takes (the others run as separate launches)
+    auto eligible = [&](int i) {
+        return (mode == MODE_U8 || mode == MODE_U16 || mode == MODE_F64) &&
+               batch_kw_ok(p[i].window[1]) && p[i].shape[0] < (1ll << 30) &&
+               p[i].shape[1] < (1ll << 28) &&   // rows are raw buffers (< 2^31 bytes)
+               fast2d_lds_per_wave(mode, kBatchR, p[i].window[0]) <= 64 * 1024;
+    };
+    // waves per workgroup: the largest (at most the requested) whose LDS rings fit in 64 KB
+    int lds_need = 0;
+    int64_t tile_rows_total = 0;   // sum over pairs of output rows x tile columns
+    for (int i = 0; i < n; i++) {
+        if (!eligible(i)) continue;
+        lds_need = std::max(lds_need, fast2d_lds_per_wave(mode, kBatchR, p[i].window[0]));
+        int64_t osh[3];
+        swc_output_shape(&p[i], osh);
+        const bool contig = p[i].step[1] == 1 && p[i].border != SWC_BORDER_VALID;
+        const int wq = contig ? fast2d_wq_aligned(kBatchR, p[i].window[1])
+                              : (kWave * kBatchR - (kBatchR - 1) - p[i].window[1]) / p[i].step[1] + 1;
+        tile_rows_total += osh[0] * ((osh[1] + wq - 1) / wq);
+    }
+    lds_need = (lds_need + 15) & ~15;
+    if (wpb == 0) wpb = 4;
+    while (wpb > 1 && (int64_t)wpb * lds_need > 64 * 1024) wpb /= 2;
+    // persistent grid: a few waves per SIMD
+    const int64_t target = (int64_t)cus * 4 * (minw > 0 ? minw : 2);
+    // tile height: about four tiles per persistent wave, 16..128 rows
+    if (TH == 0)
+        TH = (int)std::min<int64_t>(128, std::max<int64_t>(16, tile_rows_total / (4 * target)));
 
     swc_batch_plan* plan = new swc_batch_plan();
     plan->mode = mode;
@@ -147,7 +177,9 @@ swc_status swc_batch_plan_create(int32_t n, const swc_problem* p, const void* co
     std::vector<BatchItem> items;
     std::vector<int> order(n);
     for (int i = 0; i < n; i++) order[i] = i;
-    // group by (window width, alignment) so concurrent waves share code
+    // widest windows first (their tiles cost the most, so the tail of the
+    // persistent loop is made of cheap tiles), then by alignment so
+    // concurrent waves share code
     auto vec_of = [&](int i) {
         const size_t esz = p[i].dtype == SWC_U8 ? 1 : (p[i].dtype == SWC_U16 ? 2 : 4);
         const size_t va = esz * kBatchR;
@@ -155,7 +187,7 @@ swc_status swc_batch_plan_create(int32_t n, const swc_problem* p, const void* co
                 p[i].shape[1] % kBatchR == 0) ? 1 : 0;
     };
     std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
-        if (p[a].window[1] != p[b].window[1]) return p[a].window[1] < p[b].window[1];
+        if (p[a].window[1] != p[b].window[1]) return p[a].window[1] > p[b].window[1];
         return vec_of(a) > vec_of(b);
     });
     int64_t tile0 = 0;
@@ -165,11 +197,7 @@ swc_status swc_batch_plan_create(int32_t n, const swc_problem* p, const void* co
         const swc_problem& q = p[i];
         int64_t osh[3];
         swc_output_shape(&q, osh);
-        const bool fast = (mode == MODE_U8 || mode == MODE_U16 || mode == MODE_F64) &&
-                          batch_kw_ok(q.window[1]) && q.shape[0] < (1ll << 30) &&
-                          q.shape[1] < (1ll << 28) &&   // rows are raw buffers (< 2^31 bytes)
-                          (int64_t)fast2d_lds_per_wave(mode, kBatchR, q.window[0]) * wpb <=
-                              64 * 1024;
+        const bool fast = eligible(i);
         LaunchCfg L;
         L.R = kBatchR;
         L.TH = TH;
@@ -230,8 +258,7 @@ swc_status swc_batch_plan_create(int32_t n, const swc_problem* p, const void* co
     plan->n_items = (int)items.size();
     plan->total_tiles = tile0;
     plan->lds_stride = (lds_max + 15) & ~15;
-    // persistent grid: a few waves per SIMD, never more than the work
-    const int64_t target = (int64_t)cus * 4 * (minw > 0 ? minw : 2);
+    // never more waves than the work
     plan->nwaves = std::max<int64_t>(1, std::min<int64_t>(target, tile0));
     plan->d_items = nullptr;
     if (!items.empty()) {

@@ -333,7 +333,11 @@ hipError_t launch_corr2d(const swc_problem& p, const int64_t* oshape, const Laun
     // addressed as raw buffers of at most 2^31 - 1 bytes)
     const bool dims32 = g.H < ((int64_t)1 << 31) - 2 * kWave * 8 &&
                         g.W * 4 < ((int64_t)1 << 31) - 2 * kWave * 8 * 4;
-    const size_t smem_f = (size_t)L.wpb * fast2d_lds_per_wave(mode, L.R, g.kh);
+    // waves per workgroup: as requested, halved while the LDS rings of the
+    // workgroup would exceed 64 KB
+    int wpb_f = L.wpb;
+    while (wpb_f > 1 && (size_t)wpb_f * fast2d_lds_per_wave(mode, L.R, g.kh) > 64 * 1024) wpb_f /= 2;
+    const size_t smem_f = (size_t)wpb_f * fast2d_lds_per_wave(mode, L.R, g.kh);
     if (!(force & 2) && dims32 && fast2d_supported(mode, L.R, g.kw) && smem_f <= 64 * 1024) {
         P2DF f;
         f.x = x;
@@ -367,8 +371,8 @@ hipError_t launch_corr2d(const swc_problem& p, const int64_t* oshape, const Laun
         if (TH <= 0) {
             // one round of resident waves: as many tile rows as the free wave
             // slots allow across the tile columns, each as tall as that needs
-            const int64_t slots = (int64_t)device_cus() * L.wpb *
-                                  fast2d_blocks_per_cu(mode, L.R, g.kw, vec, L.wpb, smem_f);
+            const int64_t slots = (int64_t)device_cus() * wpb_f *
+                                  fast2d_blocks_per_cu(mode, L.R, g.kw, vec, wpb_f, smem_f);
             const int64_t ty = std::max<int64_t>(1, slots / std::max<int64_t>(1, tiles_x));
             TH = (int)std::min<int64_t>(4096, std::max<int64_t>(4, (g.OH + ty - 1) / ty));
         }
@@ -383,10 +387,10 @@ hipError_t launch_corr2d(const swc_problem& p, const int64_t* oshape, const Laun
         const double chain = 2.0 * th_ext + 2.0 * g.kw + 2.0 * L.R + 2.0;
         const double nterms = (double)(g.kh + 1) * (g.kw + 1);
         f.cert_g = cert_factor(mode, (double)g.kh * g.kw, chain, nterms);
-        const int gridf = (int)((ntf + L.wpb - 1) / L.wpb);
-        if (mode == MODE_U8) return launch_fast2d_modeu8(f, L.R, g.kw, vec, gridf, L.wpb, smem_f, s);
-        if (mode == MODE_U16) return launch_fast2d_modeu16(f, L.R, g.kw, vec, gridf, L.wpb, smem_f, s);
-        return launch_fast2d_modef64(f, L.R, g.kw, vec, gridf, L.wpb, smem_f, s);
+        const int gridf = (int)((ntf + wpb_f - 1) / wpb_f);
+        if (mode == MODE_U8) return launch_fast2d_modeu8(f, L.R, g.kw, vec, gridf, wpb_f, smem_f, s);
+        if (mode == MODE_U16) return launch_fast2d_modeu16(f, L.R, g.kw, vec, gridf, wpb_f, smem_f, s);
+        return launch_fast2d_modef64(f, L.R, g.kw, vec, gridf, wpb_f, smem_f, s);
     }
 
     // generic LDS-row kernel
