@@ -10,13 +10,12 @@
 // so a row of S values is  carry + (prefix over the row of d_e = v_e - v_{e-k}):
 // an in-lane prefix over R positions, a wavefront scan of the lane totals
 // (DPP row shifts + row broadcasts) and the carry from the previous row.
-// Entering values come from HBM (coalesced); the value k positions back is
-// read from a per-wave LDS ring that holds the last k + 64R positions, split
-// into R sub-rings by position mod R so that every LDS access of a wavefront
-// touches consecutive words.  Windows whose ring does not fit in LDS re-read
-// the leaving values from global memory instead (they were read k positions
-// earlier by the same wave and are normally still in L2).  The carry starts
-// from a direct sum of the k positions before the segment.
+// Entering values and the values k positions back are both read through
+// raw buffers over the wave's span (the latter were read by the same wave a
+// few rows earlier and come from L2); positions outside the array read as
+// zero.  All per-lane index arithmetic is 32-bit, relative to the span
+// start, and the next row's loads are in flight while a row is processed.
+// The carry starts from a direct sum of the k positions before the segment.
 #include "swc_device.hpp"
 #include "swc_internal.h"
 
@@ -36,7 +35,7 @@ struct P1D {
     double cert_g;
     int64_t seg;          // outputs per wave
     int64_t n_waves;
-    int ring;             // ring positions (power of two, multiple of R)
+    int vst;              // output base 16-byte aligned: whole-vector stores allowed
 };
 
 constexpr int kR1 = 8;    // positions per lane per row
@@ -127,162 +126,182 @@ __device__ __forceinline__ Ch<M> ch_diff(float x, float y, float xo, float yo, i
 
 template <int M, class T> __device__ __forceinline__ float as_val(T v) { return (float)v; }
 
-template <int M, bool RING>
+// Raw buffer over one wave's span of an input array: position d of the span
+// (span position 0 = array index e_base) is read at byte offset d * esz;
+// positions outside the array read as zero (out-of-range offsets).
+struct SpanBuf {
+    __amdgpu_buffer_rsrc_t rs;
+    int shift;      // e_base - max(e_base, 0) (<= 0), in elements
+    bool aligned;   // buffer base 16-byte aligned
+};
+
+constexpr int kBufWord3_1d = 0x00020000;   // raw buffer access (gfx9 family)
+
+template <class T>
+__device__ __forceinline__ SpanBuf span_buf(const T* A, int64_t N, int64_t e_base)
+{
+    const int64_t eb0 = e_base > 0 ? e_base : 0;
+    const int64_t avail = N - eb0 > 0 ? N - eb0 : 0;
+    const int64_t bytes = avail * (int64_t)sizeof(T);
+    const int nrec = (int)(bytes < 0x7FFFFFF0ll ? bytes : 0x7FFFFFF0ll);
+    SpanBuf b;
+    b.rs = __builtin_amdgcn_make_buffer_rsrc((void*)(A + eb0), (short)0, nrec, kBufWord3_1d);
+    b.shift = (int)(e_base - eb0);
+    b.aligned = ((uintptr_t)(A + eb0) & 15) == 0;
+    return b;
+}
+
+template <class T>
+__device__ __forceinline__ float span_load(const SpanBuf& b, int d)
+{
+    // positions before the array get an offset far beyond any record count
+    // (never a wrapped negative offset)
+    const int o = d + b.shift;
+    const uint32_t off = o >= 0 ? (uint32_t)o * (uint32_t)sizeof(T) : 0x80000000u;
+    if constexpr (sizeof(T) == 4) {
+        return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(b.rs, off, 0, 0));
+    } else if constexpr (sizeof(T) == 2) {
+        return (float)__builtin_amdgcn_raw_buffer_load_b16(b.rs, off, 0, 0);
+    } else {
+        return (float)__builtin_amdgcn_raw_buffer_load_b8(b.rs, off, 0, 0);
+    }
+}
+
+// R consecutive span positions d0 .. d0+R-1.  f32 input with the whole run
+// inside the array and 16-byte aligned: 16-byte loads; otherwise one load
+// per element.
+template <class T, int R>
+__device__ __forceinline__ void span_load_run(const SpanBuf& b, int d0, bool whole, float (&v)[R])
+{
+    if constexpr (sizeof(T) == 4 && R % 4 == 0) {
+        if (whole && b.aligned && ((d0 + b.shift) & 3) == 0) {
+            const uint32_t off = (uint32_t)(d0 + b.shift) * 4u;
+#pragma unroll
+            for (int i = 0; i < R; i += 4) {
+                typedef uint32_t u4 __attribute__((ext_vector_type(4)));
+                const u4 w = __builtin_amdgcn_raw_buffer_load_b128(b.rs, off + 4u * i, 0, 0);
+                v[i] = __uint_as_float(w.x);
+                v[i + 1] = __uint_as_float(w.y);
+                v[i + 2] = __uint_as_float(w.z);
+                v[i + 3] = __uint_as_float(w.w);
+            }
+            return;
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < R; j++) v[j] = span_load<T>(b, d0 + j);
+}
+
+// One row of R window-end positions per lane: entering and leaving values.
+template <int R> struct Row1 {
+    float a[R], b[R], ao[R], bo[R];
+};
+
+template <int M>
 __global__ void __launch_bounds__(256) corr1d_kernel(P1D g)
 {
     using T = typename Tr<M>::T;
     constexpr int R = kR1;
     constexpr bool kFloat = !Tr<M>::kInt;
-    extern __shared__ __attribute__((aligned(16))) char smem[];
     const int lane = threadIdx.x & (kWave - 1);
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);   // wave-uniform
     const int wpb = blockDim.x / kWave;
     const int64_t w = (int64_t)xcd_remap(blockIdx.x, gridDim.x) * wpb + wv;
     if (w >= g.n_waves) return;
 
-    const T* __restrict__ X = (const T*)g.x;
-    const T* __restrict__ Y = (const T*)g.y;
     const int64_t N = g.N;
     const int k = g.k;
-    // ring: R sub-rings of ring/R entries for x, y (values as float) and a
-    // missing bit per position
-    const int ring = g.ring;
-    const int sub = ring / R;
-    const size_t wave_bytes = (size_t)ring * (kFloat ? 9 : 8);
-    float* rx = (float*)(smem + (size_t)wv * wave_bytes);
-    float* ry = rx + ring;
-    uint8_t* rm = (uint8_t*)(ry + ring);
-
     const int64_t p_first = w * g.seg;
     const int64_t p_last = min(p_first + g.seg, g.ON) - 1;
     const int64_t e_first = p_first * g.s + g.off + k - 1;   // window end of p_first
     const int64_t e_last = p_last * g.s + g.off + k - 1;
     const int kal = ((k + R - 1) / R) * R;
-    const int64_t e_base = e_first - kal;                     // ring position 0
+    // span positions are relative to e_base; everything below is 32-bit
+    const int64_t e_base = e_first - kal;
+    const int d_end = (int)(e_last - e_base);                // last window end
+    const int64_t nlim64 = N - e_base;                       // positions d < nlim are < N
+    const int nlim = (int)(nlim64 > 0x3FFFFFFF ? 0x3FFFFFFF : (nlim64 < -0x3FFFFFFF ? -0x3FFFFFFF : nlim64));
+    const int dmin = (int)(e_base < 0 ? -e_base : 0);        // positions d >= dmin are >= 0
+    const SpanBuf bx = span_buf<T>((const T*)g.x, N, e_base);
+    const SpanBuf by = span_buf<T>((const T*)g.y, N, e_base);
+    const int pstep = g.s;
 
-    auto load_val = [&](const T* __restrict__ A, int64_t e) -> float {
-        return (e >= 0 && e < N) ? (float)A[e] : 0.f;
-    };
-    auto slot_of = [&](int64_t e, int& sr, int& si) {
-        const int64_t d = e - e_base;                  // >= 0 for every position used
-        sr = (int)(d % R);
-        si = (int)((d / R) & (sub - 1));
-    };
-
-    // ---- init: positions [e_first - kal, e_first - 1] into the ring; carry
-    //      = sum over [e_first - k, e_first - 1] ----
+    // ---- carry = sums over span positions [kal - k, kal - 1] ----
     Ch<M> part = ch_zero<M>();
     float mx = 0.f, my = 0.f;
-    for (int i = lane; i < kal; i += kWave) {
-        const int64_t e = e_base + i;
-        float a = load_val(X, e), b = load_val(Y, e);
+    for (int i = kal - k + lane; i < kal; i += kWave) {
+        float a = span_load<T>(bx, i), b = span_load<T>(by, i);
         int m = 0;
         if constexpr (kFloat) {
             m = (is_missing(a, g.miss_thr) || is_missing(b, g.miss_thr)) ? 1 : 0;
             if (m) { a = 0.f; b = 0.f; }
         }
-        if constexpr (RING) {
-            int sr, si;
-            slot_of(e, sr, si);
-            rx[sr * sub + si] = a;
-            ry[sr * sub + si] = b;
-            rm[sr * sub + si] = (uint8_t)m;
-        }
-        if (i >= kal - k) {
-            Ch<M> d = ch_diff<M>(a, b, 0.f, 0.f, m, 0);
-            ch_add<M>(part, d);
-            mx = fmaxf(mx, __builtin_fabsf(a));
-            my = fmaxf(my, __builtin_fabsf(b));
-        }
+        ch_add<M>(part, ch_diff<M>(a, b, 0.f, 0.f, m, 0));
+        mx = fmaxf(mx, __builtin_fabsf(a));
+        my = fmaxf(my, __builtin_fabsf(b));
     }
     Ch<M> carry;
-    {
-        Ch<M> sc;
-        sc.x = lane63(wave_incl_scan(part.x));
-        sc.y = lane63(wave_incl_scan(part.y));
-        sc.xx = lane63(wave_incl_scan(part.xx));
-        sc.yy = lane63(wave_incl_scan(part.yy));
-        sc.xy = lane63(wave_incl_scan(part.xy));
-        sc.miss = lane63(wave_incl_scan(part.miss));
-        carry = sc;
-    }
+    carry.x = lane63(wave_incl_scan(part.x));
+    carry.y = lane63(wave_incl_scan(part.y));
+    carry.xx = lane63(wave_incl_scan(part.xx));
+    carry.yy = lane63(wave_incl_scan(part.yy));
+    carry.xy = lane63(wave_incl_scan(part.xy));
+    carry.miss = lane63(wave_incl_scan(part.miss));
     float MX = wave_max(mx), MY = wave_max(my);
-    wave_lds_sync();
-
-    // certification factor for this wave's chain (float input)
     const double gcert = g.cert_g;
+    const bool has_flags = g.flags != nullptr;
+    const bool fill = g.border == BORDER_FILL;
 
-    for (int64_t row = e_first; row <= e_last; row += kWave * R) {
-        const int64_t e0 = row + (int64_t)lane * R;
-        float a[R], b[R], ao[R], bo[R];
+    // outputs of this wave as raw buffers (out-of-range offsets drop stores)
+    const int nout = (int)(p_last - p_first + 1);
+    const __amdgpu_buffer_rsrc_t rc =
+        __builtin_amdgcn_make_buffer_rsrc(g.c + p_first, (short)0, nout * 4, kBufWord3_1d);
+    const __amdgpu_buffer_rsrc_t rf = __builtin_amdgcn_make_buffer_rsrc(
+        has_flags ? (void*)(g.flags + p_first) : (void*)g.c, (short)0, has_flags ? nout : 0,
+        kBufWord3_1d);
+
+    auto load_row = [&](int rrel, Row1<R>& r) __attribute__((always_inline)) {
+        const int d0 = rrel + lane * R;
+        const bool whole_in = (d0 >= dmin) && (d0 + R - 1 < nlim);
+        const bool whole_out = (d0 - k >= dmin) && (d0 - k + R - 1 < nlim);
+        span_load_run<T, R>(bx, d0, whole_in, r.a);
+        span_load_run<T, R>(by, d0, whole_in, r.b);
+        span_load_run<T, R>(bx, d0 - k, whole_out, r.ao);
+        span_load_run<T, R>(by, d0 - k, whole_out, r.bo);
+    };
+
+    auto process = [&](int rrel, Row1<R>& r) __attribute__((always_inline)) {
+        const int d0 = rrel + lane * R;
         int m[R], mo[R];
-        // entering values
-#pragma unroll
-        for (int j = 0; j < R; j++) {
-            a[j] = load_val(X, e0 + j);
-            b[j] = load_val(Y, e0 + j);
-        }
         float lmx = 0.f, lmy = 0.f;
 #pragma unroll
         for (int j = 0; j < R; j++) {
             m[j] = 0;
+            mo[j] = 0;
             if constexpr (kFloat) {
-                m[j] = (is_missing(a[j], g.miss_thr) || is_missing(b[j], g.miss_thr)) ? 1 : 0;
-                a[j] = m[j] ? 0.f : a[j];
-                b[j] = m[j] ? 0.f : b[j];
-                lmx = fmaxf(lmx, __builtin_fabsf(a[j]));
-                lmy = fmaxf(lmy, __builtin_fabsf(b[j]));
-            }
-        }
-        if constexpr (RING) {
-            // park the entering values first: for k < 64R a position's
-            // leaving value can be an entering value of this same row
-            wave_lds_sync();   // previous row's reads are ordered before these writes
-#pragma unroll
-            for (int j = 0; j < R; j++) {
-                int sr, si;
-                slot_of(e0 + j, sr, si);
-                rx[sr * sub + si] = a[j];
-                ry[sr * sub + si] = b[j];
-                rm[sr * sub + si] = (uint8_t)m[j];
-            }
-            wave_lds_sync();
-            // leaving values (k positions back) from the ring
-#pragma unroll
-            for (int j = 0; j < R; j++) {
-                int sr, si;
-                slot_of(e0 + j - k, sr, si);
-                ao[j] = rx[sr * sub + si];
-                bo[j] = ry[sr * sub + si];
-                mo[j] = rm[sr * sub + si];
-            }
-        } else {
-            // leaving values re-read from global memory
-#pragma unroll
-            for (int j = 0; j < R; j++) {
-                ao[j] = load_val(X, e0 + j - k);
-                bo[j] = load_val(Y, e0 + j - k);
-                mo[j] = 0;
-                if constexpr (kFloat) {
-                    mo[j] = (is_missing(ao[j], g.miss_thr) || is_missing(bo[j], g.miss_thr)) ? 1 : 0;
-                    ao[j] = mo[j] ? 0.f : ao[j];
-                    bo[j] = mo[j] ? 0.f : bo[j];
-                }
+                m[j] = (is_missing(r.a[j], g.miss_thr) | is_missing(r.b[j], g.miss_thr)) ? 1 : 0;
+                mo[j] = (is_missing(r.ao[j], g.miss_thr) | is_missing(r.bo[j], g.miss_thr)) ? 1 : 0;
+                r.a[j] = m[j] ? 0.f : r.a[j];
+                r.b[j] = m[j] ? 0.f : r.b[j];
+                r.ao[j] = mo[j] ? 0.f : r.ao[j];
+                r.bo[j] = mo[j] ? 0.f : r.bo[j];
+                lmx = fmaxf(lmx, __builtin_fabsf(r.a[j]));
+                lmy = fmaxf(lmy, __builtin_fabsf(r.b[j]));
             }
         }
         if constexpr (kFloat) {
             MX = fmaxf(MX, wave_max(lmx));
             MY = fmaxf(MY, wave_max(lmy));
         }
-        // in-lane prefix of d
+        // in-lane prefix of the differences
         Ch<M> P[R];
 #pragma unroll
         for (int j = 0; j < R; j++) {
-            P[j] = ch_diff<M>(a[j], b[j], ao[j], bo[j], m[j], mo[j]);
+            P[j] = ch_diff<M>(r.a[j], r.b[j], r.ao[j], r.bo[j], m[j], mo[j]);
             if (j > 0) ch_add<M>(P[j], P[j - 1]);
         }
-        // wavefront scan of lane totals -> exclusive offsets
-        Ch<M> tot = P[R - 1];
+        // wavefront scan of the lane totals -> exclusive offsets
+        const Ch<M> tot = P[R - 1];
         Ch<M> inc;
         inc.x = wave_incl_scan(tot.x);
         inc.y = wave_incl_scan(tot.y);
@@ -306,54 +325,162 @@ __global__ void __launch_bounds__(256) corr1d_kernel(P1D g)
         const double gx = gcert * (double)MX * (double)MX;
         const double gy = gcert * (double)MY * (double)MY;
 
-        // ---- outputs ending at e0 + j ----
+        // ---- outputs ending at span positions d0 + j ----
+        // window of end d: span positions [d-k+1, d]; inside the array when
+        // d - k + 1 >= dmin and d < nlim (uniform test for the whole row)
+        const bool row_inside = (rrel - k + 1 >= dmin) && (rrel + kWave * R - 1 < nlim);
+        float cv[R];
+        uint32_t flw[R / 4] = {};
+        bool any_pend = false;
+        uint32_t outm = 0;   // which of the R positions are output window ends
 #pragma unroll
         for (int j = 0; j < R; j++) {
-            const int64_t e = e0 + j;
-            if (e > e_last) continue;
-            const int64_t qs = e - (int64_t)(g.off + k - 1);     // = p*s
-            if (qs < 0) continue;
-            int64_t p = qs;
-            if (g.s != 1) {
-                p = qs / g.s;
-                if (p * g.s != qs) continue;
-            }
-            if (p < p_first || p > p_last) continue;
+            const int d = d0 + j;
+            const int qs = d - kal;                                 // = (p - p_first) * s
+            const bool is_out = (d <= d_end) && (qs >= 0) && (pstep == 1 || (qs % pstep) == 0);
+            outm |= is_out ? (1u << j) : 0u;
             Ch<M> S = base;
             ch_add<M>(S, P[j]);
-            const int64_t lo = e - k + 1;
-            const bool bord = lo < 0 || e > N - 1;
-            const int64_t nl = (e < N - 1 ? e : N - 1) - (lo > 0 ? lo : 0) + 1;
-            uint8_t fl = (g.border == BORDER_FILL && bord) ? FL_BORDER : 0;
-            float cv = 0.f;
-            if (!fl && S.miss > 0) fl = FL_MISSING;
-            if (!fl) {
-                const double dn = (double)nl;
+            double dn;
+            bool bord;
+            if (row_inside) {
+                dn = (double)k;
+                bord = false;
+            } else {
+                const int lo = d - k + 1;
+                bord = lo < dmin || d >= nlim;
+                const int clo = lo > dmin ? lo : dmin, chi = d < nlim - 1 ? d : nlim - 1;
+                dn = (double)(chi - clo + 1);
+            }
+            const bool fb = fill & bord;
+            double Nn, Vx, Vy;
+            if constexpr (kFloat) {
+                Nn = __builtin_fma(dn, S.xy, -(S.x * S.y));
+                Vx = __builtin_fma(dn, S.xx, -(S.x * S.x));
+                Vy = __builtin_fma(dn, S.yy, -(S.y * S.y));
+            } else {
+                Nn = __builtin_fma(dn, S.xy, -(S.x * S.y));
+                Vx = __builtin_fma(dn, S.xx, -(S.x * S.x));
+                Vy = __builtin_fma(dn, S.yy, -(S.y * S.y));
+            }
+            const double q = Vx * Vy;
+            float c;
+            bool bad, pend;
+            uint32_t fl;
+            if constexpr (kFloat) {
+                const bool cert = (Vx > gx) & (Vy > gy);
+                const double rr = __builtin_amdgcn_rsq(q);
+                const double e = __builtin_fma(-(q * rr), rr, 1.0);
+                const double a0 = Nn * rr;
+                c = clamp_unit(__builtin_fma(0.5 * a0, e, a0));
+                const bool miss = S.miss > 0;
+                bad = fb | miss;
+                pend = (!bad) & ((!cert) | ((g.force & 1) != 0));
+                fl = fb ? FL_BORDER : (miss ? FL_MISSING : 0u);
+            } else {
+                const double rr = __builtin_amdgcn_rsq(q);
+                const double t = q * rr;
+                const double e = __builtin_fma(-t, rr, 1.0);
+                const double a0 = Nn * rr;
+                const double a = __builtin_fma(0.5 * a0, e, a0);
+                const uint32_t lo29 = (uint32_t)__double_as_longlong(a) & 0x1FFFFFFFu;
+                const bool amb = (lo29 - (0x10000000u - (1u << 15))) <= (2u << 15);
+                c = (float)a;
+                bad = fb | (q == 0.0);
+                pend = (!bad) & (amb | ((g.force & 1) != 0));
+                fl = fb ? FL_BORDER : ((Vx == 0.0 ? FL_ZVAR_X : 0u) | (Vy == 0.0 ? FL_ZVAR_Y : 0u));
+            }
+            asm volatile("" : "+v"(c));
+            cv[j] = bad ? g.invalid : c;
+            flw[j / 4] |= (bad ? fl : 0u) << (8 * (j % 4));
+            any_pend = any_pend | (pend & is_out);
+        }
+        // rare path: two-pass recomputation (float) / exact rounding (integer)
+        if (__builtin_amdgcn_ballot_w64(any_pend)) {
+#pragma unroll
+            for (int j = 0; j < R; j++) {
+                const int d = d0 + j;
+                if (!((outm >> j) & 1u)) continue;
+                Ch<M> S = base;
+                ch_add<M>(S, P[j]);
+                const int lo = d - k + 1;
+                const bool bord = lo < dmin || d >= nlim;
+                if (fill && bord) continue;
+                const int clo = lo > dmin ? lo : dmin, chi = d < nlim - 1 ? d : nlim - 1;
+                const double dn = (double)(chi - clo + 1);
+                const double Nn = __builtin_fma(dn, S.xy, -(S.x * S.y));
+                const double Vx = __builtin_fma(dn, S.xx, -(S.x * S.x));
+                const double Vy = __builtin_fma(dn, S.yy, -(S.y * S.y));
                 if constexpr (kFloat) {
-                    const double Nn = __builtin_fma(dn, S.xy, -(S.x * S.y));
-                    const double Vx = __builtin_fma(dn, S.xx, -(S.x * S.x));
-                    const double Vy = __builtin_fma(dn, S.yy, -(S.y * S.y));
-                    const bool cert = (Vx > gx) && (Vy > gy) && !(g.force & 1);
-                    if (cert) {
-                        cv = clamp_unit(Nn * rsqrt64(Vx * Vy));
-                    } else {
-                        const int64_t cl = lo > 0 ? lo : 0, ch = e < N - 1 ? e : N - 1;
-                        fl = twopass_window((const float*)g.x, (const float*)g.y, 0, 0, 0, 0, 0,
-                                            0, cl, ch, &cv);
-                    }
+                    if (S.miss > 0) continue;
+                    if ((Vx > gx) && (Vy > gy) && !(g.force & 1)) continue;
+                    float c2 = 0.f;
+                    const int64_t cl = e_base + clo, ch = e_base + chi;
+                    const uint8_t f2 = twopass_window((const float*)g.x, (const float*)g.y, 0, 0, 0,
+                                                      0, 0, 0, cl, ch, &c2);
+                    cv[j] = f2 ? g.invalid : c2;
+                    flw[j / 4] = (flw[j / 4] & ~(0xFFu << (8 * (j % 4)))) | ((uint32_t)f2 << (8 * (j % 4)));
                 } else {
-                    // exact integers: every sum below 2^53
-                    const double Nn = __builtin_fma(dn, S.xy, -(S.x * S.y));
-                    const double Vx = __builtin_fma(dn, S.xx, -(S.x * S.x));
-                    const double Vy = __builtin_fma(dn, S.yy, -(S.y * S.y));
-                    fl = (Vx == 0.0 ? FL_ZVAR_X : 0) | (Vy == 0.0 ? FL_ZVAR_Y : 0);
-                    if (!fl) cv = rn32_certified(Nn, Vx, Vy, (g.force & 1) != 0);
+                    if (Vx == 0.0 || Vy == 0.0) continue;
+                    cv[j] = rn32_certified(Nn, Vx, Vy, (g.force & 1) != 0);
                 }
             }
-            if (fl) cv = g.invalid;
-            g.c[p] = cv;
-            if (g.flags) g.flags[p] = fl;
         }
+        // ---- stores: output index p - p_first = qs / s ----
+        if (pstep == 1) {
+            const int o0 = d0 - kal;                                  // output of position d0
+            const bool whole = g.vst && (o0 >= 0) && (o0 + R - 1 < nout) && ((o0 & 3) == 0) &&
+                               ((p_first & 3) == 0);
+            if (whole) {
+#pragma unroll
+                for (int j = 0; j < R; j += 4) {
+                    typedef uint32_t u4 __attribute__((ext_vector_type(4)));
+                    const u4 v = {__float_as_uint(cv[j]), __float_as_uint(cv[j + 1]),
+                                  __float_as_uint(cv[j + 2]), __float_as_uint(cv[j + 3])};
+                    __builtin_amdgcn_raw_buffer_store_b128(v, rc, (uint32_t)(o0 + j) * 4u, 0, 0);
+                }
+                if (has_flags) {
+#pragma unroll
+                    for (int j = 0; j < R; j++)
+                        __builtin_amdgcn_raw_buffer_store_b8((uint8_t)(flw[j / 4] >> (8 * (j % 4))),
+                                                             rf, (uint32_t)(o0 + j), 0, 0);
+                }
+                return;
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < R; j++) {
+            const int d = d0 + j;
+            const int qs = d - kal;
+            // byte offsets; positions that are not outputs of this wave get an
+            // offset beyond any record count (applied after the scaling, so
+            // it cannot wrap)
+            const bool is_o = (outm >> j) & 1u;
+            const uint32_t o = (uint32_t)(qs / pstep);
+            __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(cv[j]), rc,
+                                                  is_o ? o * 4u : 0x80000000u, 0, 0);
+            if (has_flags)
+                __builtin_amdgcn_raw_buffer_store_b8((uint8_t)(flw[j / 4] >> (8 * (j % 4))), rf,
+                                                     is_o ? o : 0x80000000u, 0, 0);
+        }
+    };
+
+    // rows of R*64 window ends, the next row's loads in flight while one is
+    // processed (two register sets, alternating)
+    constexpr int kRow = kWave * R;
+    Row1<R> A, B;
+    int rrel = kal;
+    load_row(rrel, A);
+    while (true) {
+        const int r1 = rrel + kRow;
+        if (r1 <= d_end) load_row(r1, B);
+        process(rrel, A);
+        if (r1 > d_end) break;
+        const int r2 = r1 + kRow;
+        if (r2 <= d_end) load_row(r2, A);
+        process(r1, B);
+        if (r2 > d_end) break;
+        rrel = r2;
     }
 }
 
@@ -361,41 +488,19 @@ __global__ void __launch_bounds__(256) corr1d_kernel(P1D g)
 // Host side
 // ---------------------------------------------------------------------------
 
-static int ring_positions(int k)
-{
-    const int need = ((k + kR1 - 1) / kR1) * kR1 + kWave * kR1;
-    int r = kWave * kR1;
-    while (r < need) r <<= 1;
-    return r;
-}
-
-static size_t lds_per_wave_1d(int mode, int k)
-{
-    return (size_t)ring_positions(k) * (mode >= MODE_F64 ? 9 : 8);
-}
-
-// The LDS ring is used when it fits in 64 KB per workgroup.
-static bool ring_fits_1d(int mode, int k, int wpb)
-{
-    return lds_per_wave_1d(mode, k) * (size_t)wpb <= 64 * 1024;
-}
-
 bool cfg_ok_1d(const swc_problem& p, const LaunchCfg& L)
 {
     const int mode = mode_of(p.dtype, p.accum);
     if (mode != MODE_U8 && mode != MODE_U16 && mode != MODE_F64) return false;
     if (!(L.wpb == 1 || L.wpb == 2 || L.wpb == 4)) return false;
-    if (L.TH < 1 || L.TH > (1 << 20)) return false;
+    if (L.TH < 1 || L.TH > (1 << 16)) return false;
     return L.R == kR1;
 }
 
 template <int M>
-static hipError_t go1d(const P1D& g, int grid, int wpb, size_t smem, hipStream_t s)
+static hipError_t go1d(const P1D& g, int grid, int wpb, hipStream_t s)
 {
-    if (smem)
-        hipLaunchKernelGGL((corr1d_kernel<M, true>), dim3(grid), dim3(wpb * kWave), smem, s, g);
-    else
-        hipLaunchKernelGGL((corr1d_kernel<M, false>), dim3(grid), dim3(wpb * kWave), 0, s, g);
+    hipLaunchKernelGGL((corr1d_kernel<M>), dim3(grid), dim3(wpb * kWave), 0, s, g);
     return hipGetLastError();
 }
 
@@ -422,18 +527,16 @@ hipError_t launch_corr1d(const swc_problem& p, const int64_t* oshape, const Laun
     const int64_t span = (int64_t)L.TH * kWave * kR1;
     g.seg = span / g.s > 0 ? span / g.s : 1;
     g.n_waves = (g.ON + g.seg - 1) / g.seg;
-    g.ring = ring_positions(g.k);
+    g.vst = ((uintptr_t)c % 16 == 0) ? 1 : 0;
     const double rows = (double)(g.seg * g.s) / (kWave * kR1) + 1.0;
     const double chain = 2.0 * (double)(g.seg * g.s + g.k) + 16.0 * rows + 64.0;
     g.cert_g = cert_factor(mode, (double)g.k, chain, (double)g.k + 3.0);
     const int64_t grid64 = (g.n_waves + L.wpb - 1) / L.wpb;
     if (grid64 >= ((int64_t)1 << 31)) return hipErrorInvalidValue;
-    const size_t smem =
-        ring_fits_1d(mode, g.k, L.wpb) ? lds_per_wave_1d(mode, g.k) * (size_t)L.wpb : 0;
     switch (mode) {
-    case MODE_U8: return go1d<MODE_U8>(g, (int)grid64, L.wpb, smem, s);
-    case MODE_U16: return go1d<MODE_U16>(g, (int)grid64, L.wpb, smem, s);
-    default: return go1d<MODE_F64>(g, (int)grid64, L.wpb, smem, s);
+    case MODE_U8: return go1d<MODE_U8>(g, (int)grid64, L.wpb, s);
+    case MODE_U16: return go1d<MODE_U16>(g, (int)grid64, L.wpb, s);
+    default: return go1d<MODE_F64>(g, (int)grid64, L.wpb, s);
     }
 }
 
