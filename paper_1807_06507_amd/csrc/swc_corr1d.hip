@@ -132,7 +132,6 @@ template <int M, class T> __device__ __forceinline__ float as_val(T v) { return 
 struct SpanBuf {
     __amdgpu_buffer_rsrc_t rs;
     int shift;      // e_base - max(e_base, 0) (<= 0), in elements
-    bool aligned;   // buffer base 16-byte aligned
 };
 
 constexpr int kBufWord3_1d = 0x00020000;   // raw buffer access (gfx9 family)
@@ -147,7 +146,6 @@ __device__ __forceinline__ SpanBuf span_buf(const T* A, int64_t N, int64_t e_bas
     SpanBuf b;
     b.rs = __builtin_amdgcn_make_buffer_rsrc((void*)(A + eb0), (short)0, nrec, kBufWord3_1d);
     b.shift = (int)(e_base - eb0);
-    b.aligned = ((uintptr_t)(A + eb0) & 15) == 0;
     return b;
 }
 
@@ -168,13 +166,13 @@ __device__ __forceinline__ float span_load(const SpanBuf& b, int d)
 }
 
 // R consecutive span positions d0 .. d0+R-1.  f32 input with the whole run
-// inside the array and 16-byte aligned: 16-byte loads; otherwise one load
-// per element.
+// inside the array: 16-byte loads (dword aligned; the memory system takes
+// unaligned vector accesses); otherwise one load per element.
 template <class T, int R>
 __device__ __forceinline__ void span_load_run(const SpanBuf& b, int d0, bool whole, float (&v)[R])
 {
     if constexpr (sizeof(T) == 4 && R % 4 == 0) {
-        if (whole && b.aligned && ((d0 + b.shift) & 3) == 0) {
+        if (whole) {
             const uint32_t off = (uint32_t)(d0 + b.shift) * 4u;
 #pragma unroll
             for (int i = 0; i < R; i += 4) {
@@ -197,8 +195,13 @@ template <int R> struct Row1 {
     float a[R], b[R], ao[R], bo[R];
 };
 
+// Two waves per SIMD for the float kernel; the integer kernels (larger
+// per-lane state) are left to the compiler.
+template <int M> constexpr int corr1d_min_waves() { return M == MODE_F64 ? 2 : 1; }
+
 template <int M>
-__global__ void __launch_bounds__(256) corr1d_kernel(P1D g)
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(corr1d_min_waves<M>(), 8)))
+corr1d_kernel(P1D g)
 {
     using T = typename Tr<M>::T;
     constexpr int R = kR1;
@@ -275,16 +278,37 @@ __global__ void __launch_bounds__(256) corr1d_kernel(P1D g)
         int m[R], mo[R];
         float lmx = 0.f, lmy = 0.f;
 #pragma unroll
-        for (int j = 0; j < R; j++) {
-            m[j] = 0;
-            mo[j] = 0;
-            if constexpr (kFloat) {
-                m[j] = (is_missing(r.a[j], g.miss_thr) | is_missing(r.b[j], g.miss_thr)) ? 1 : 0;
-                mo[j] = (is_missing(r.ao[j], g.miss_thr) | is_missing(r.bo[j], g.miss_thr)) ? 1 : 0;
-                r.a[j] = m[j] ? 0.f : r.a[j];
-                r.b[j] = m[j] ? 0.f : r.b[j];
-                r.ao[j] = mo[j] ? 0.f : r.ao[j];
-                r.bo[j] = mo[j] ? 0.f : r.bo[j];
+        for (int j = 0; j < R; j++) { m[j] = 0; mo[j] = 0; }
+        if constexpr (kFloat) {
+            // a value is missing when it is <= the threshold, NaN or +-Inf;
+            // test the row's extremes first and look at single values only
+            // when the wave's rows hold one
+            float lo = r.a[0], hi = r.a[0];
+#pragma unroll
+            for (int j = 0; j < R; j++) {
+                lo = fminf(lo, fminf(fminf(r.a[j], r.b[j]), fminf(r.ao[j], r.bo[j])));
+                hi = fmaxf(hi, fmaxf(fmaxf(r.a[j], r.b[j]), fmaxf(r.ao[j], r.bo[j])));
+            }
+            // fminf/fmaxf drop NaN operands, so NaN needs its own test
+            bool nan = false;
+#pragma unroll
+            for (int j = 0; j < R; j++)
+                nan = nan | (r.a[j] != r.a[j]) | (r.b[j] != r.b[j]) | (r.ao[j] != r.ao[j]) |
+                      (r.bo[j] != r.bo[j]);
+            const bool clean = (lo > g.miss_thr) & (hi < __builtin_inff()) & !nan;
+            if (__builtin_amdgcn_ballot_w64(!clean)) {
+#pragma unroll
+                for (int j = 0; j < R; j++) {
+                    m[j] = (is_missing(r.a[j], g.miss_thr) | is_missing(r.b[j], g.miss_thr)) ? 1 : 0;
+                    mo[j] = (is_missing(r.ao[j], g.miss_thr) | is_missing(r.bo[j], g.miss_thr)) ? 1 : 0;
+                    r.a[j] = m[j] ? 0.f : r.a[j];
+                    r.b[j] = m[j] ? 0.f : r.b[j];
+                    r.ao[j] = mo[j] ? 0.f : r.ao[j];
+                    r.bo[j] = mo[j] ? 0.f : r.bo[j];
+                }
+            }
+#pragma unroll
+            for (int j = 0; j < R; j++) {
                 lmx = fmaxf(lmx, __builtin_fabsf(r.a[j]));
                 lmy = fmaxf(lmy, __builtin_fabsf(r.b[j]));
             }
