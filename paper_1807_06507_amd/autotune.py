@@ -7,13 +7,15 @@ accumulation mode) it times candidate tile shapes on the GPU through the C ABI
 (`swc_corr_ex`, `swc_batch_plan_*`) and writes the fastest into a tuning table
 that the library loads at initialisation (`tune_table.txt` next to
 libswcorr.so, or the file named by SWC_TUNE_TABLE).  Candidates:
-  2-D:    cols_per_lane R in {4, 8}, tile rows TH, waves per workgroup
+  2-D:    cols_per_lane R in {4, 8}, tile rows TH (0 = one round of resident
+          waves), waves per workgroup
   1-D:    rows per wave TH, waves per workgroup (R fixed at 8)
-  batch:  tile rows TH, waves per workgroup (R fixed at 4)
+  3-D:    planes per wave TH, output rows per wave TY, waves per workgroup
+  batch:  tile rows TH (0 = about four tiles per wave), waves per workgroup
 Timing uses HIP events on the launch stream over several launches whose
 input buffers rotate beyond the 256 MB Infinity Cache, as the benchmark does.
 
-Table line format:  dtype ndim accum kbucket R TH wpb min_waves
+Table line format:  dtype ndim accum kbucket R TH wpb min_waves [TY]
 (kbucket 0 with ndim 2 holds the batched-launch parameters).
 """
 from __future__ import annotations
@@ -107,22 +109,25 @@ def main():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--quick", action="store_true", help="fewer candidates")
     ap.add_argument("--out", default=os.path.join(HERE, "tune_table.txt"))
-    ap.add_argument("--only", default="", help="comma list: c0,c1,c2,c3,c4b")
+    ap.add_argument("--only", default="", help="comma list: c0,c1,c2,c3,c4a,c4b")
     args = ap.parse_args()
     import torch
     import paper_1807_06507_amd as swc
     from workloads import (paper_shaped_u16, cloud_pair, precision_pair, batched_pairs,
-                           series_1d)
+                           series_1d, volume_3d)
     assert torch.cuda.is_available()
     only = set(args.only.split(",")) if args.only else None
-    ths = [8, 12, 16, 24, 32, 48] if not args.quick else [12, 24]
-    wpbs = [1, 2, 4] if not args.quick else [1, 2]
+    ths = [0, 16, 24, 32] if not args.quick else [0, 24]
+    wpbs = [1, 2, 4] if not args.quick else [2, 4]
     cand2d = [(R, th, w) for R, th, w in itertools.product([4, 8], ths, wpbs)]
     lines = []
 
     def emit(dt, nd, acc, kb, cand):
-        lines.append(f"{DT_CODE[dt]} {nd} {acc} {kb} {cand[0]} {cand[1]} {cand[2]} "
-                     f"{cand[3] if len(cand) > 3 else 0}")
+        line = (f"{DT_CODE[dt]} {nd} {acc} {kb} {cand[0]} {cand[1]} {cand[2]} "
+                f"{cand[3] if len(cand) > 3 else 0}")
+        if len(cand) > 4:
+            line += f" {cand[4]}"
+        lines.append(line)
 
     t0 = time.time()
     if only is None or "c1" in only:
@@ -141,15 +146,21 @@ def main():
             b = tune_single(x, y, (k, k), 1, "clip", cand2d, f"f32 2-D k{k}")
             emit("f32", 2, 0, kbucket(k), b[1])
     if only is None or "c3" in only:
-        pairs = batched_pairs(64, seed=1, scale=0.5)
-        candb = [(4, th, w) for th, w in itertools.product(ths, wpbs)]
+        pairs = batched_pairs(64, seed=1)
+        candb = [(4, th, w) for th, w in itertools.product([0, 32, 64, 96, 128], [0, 1, 2])]
         b = tune_batch(pairs, candb, "f32 batch")
         emit("f32", 2, 0, 0, b[1])
     if only is None or "c4b" in only:
         x, y = series_1d(1 << 26, seed=5)
-        cand1 = [(8, th, w) for th, w in itertools.product([16, 32, 64, 128, 256], [1, 2])]
+        cand1 = [(8, th, w) for th, w in itertools.product([16, 32, 64, 128, 256], [1, 2, 4])]
         b = tune_single(x, y, (1001,), 1, "clip", cand1, "f32 1-D k1001")
         emit("f32", 1, 0, kbucket(1001), b[1])
+    if only is None or "c4a" in only:
+        x, y = volume_3d((64, 256, 512), seed=4)
+        cand3 = [(4, th, w, 0, ty) for th, w, ty in itertools.product([8, 16, 32, 64], [1, 2, 4],
+                                                                      [2, 4])]
+        b = tune_single(x, y, (7, 7, 7), 1, "clip", cand3, "f32 3-D k7")
+        emit("f32", 3, 0, 7, b[1])
     with open(args.out, "w") as f:
         f.write("# swcorr tuning table: dtype ndim accum kbucket R TH wpb min_waves\n")
         f.write(f"# written by paper_1807_06507_amd.autotune on "
