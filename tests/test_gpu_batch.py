@@ -124,3 +124,32 @@ def test_batch_config_scaled():
     for p, c, fl in zip(pairs, outs, fls):
         dmax = max(dmax, _check_pair(p, c, fl))
     say(f"[batch] scaled c3: max|dc| = {dmax:.3e}")
+
+
+def test_batch_config_full_sampled():
+    """The batched configuration at full size (64 pairs, 229.7 Mpx, k from
+    {5, 7, 9, 15}, CLIP) in the launch configuration the benchmark times:
+    2000 sampled outputs of every pair plus its first row, one by one
+    against the oracle."""
+    import torch
+    import paper_1807_06507_amd as swc
+    pairs = batched_pairs(64, seed=1)
+    dev = [dict(x=to_dev(x), y=to_dev(y), window=k, step=1, border="clip") for x, y, k in pairs]
+    plan = swc.BatchPlan(dev, return_flags=True)
+    plan.launch()
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(7)
+    dmax = 0.0
+    for (x, y, k), o, f in zip(pairs, plan.outputs, plan.flags):
+        c, fl = o.cpu().numpy(), f.cpu().numpy()
+        idx = np.unique(np.concatenate([rng.integers(0, x.size, 2000), np.arange(x.shape[1])]))
+        o32, o64, ofl = oracle.corr(x, y, (k, k), 1, "clip", indices=idx)
+        cs, fs = c.ravel()[idx], fl.ravel()[idx]
+        assert np.array_equal(fs, ofl)
+        ok = ofl == 0
+        assert np.all(cs[~ok] == np.float32(-2.0))
+        if ok.any():
+            dmax = max(dmax, float(np.max(np.abs(cs[ok].astype(np.float64) - o64[ok]))))
+    assert dmax <= F32_TOL, dmax
+    say(f"[batch] full c3 (sampled): max|dc| = {dmax:.3e}, items {plan.items}")
+    plan.close()
