@@ -23,6 +23,8 @@ bool cfg_ok_3d(const swc_problem& p, const LaunchCfg& L)
     if (!(L.TY == 2 || L.TY == 4)) return false;
     for (int d = 0; d < 3; d++)
         if (p.shape[d] >= ((int64_t)1 << 30)) return false;
+    // rows are addressed as raw buffers of at most 2^31 - 1 bytes
+    if (p.shape[2] * 4 >= ((int64_t)1 << 31) - 64) return false;
     return wq3_of(p.window[2], p.step[2]) >= 1;
 }
 
@@ -71,11 +73,14 @@ hipError_t launch_corr3d(const swc_problem& p, const int64_t* oshape, const Laun
     const size_t esz = p.dtype == SWC_U8 ? 1 : (p.dtype == SWC_U16 ? 2 : 4);
     const bool vec = ((uintptr_t)x % (esz * 4) == 0) && ((uintptr_t)y % (esz * 4) == 0) &&
                      (g.W % 4 == 0);
-    const int grid = (int)((nt + L.wpb - 1) / L.wpb);
+    // waves per workgroup: halved while the LDS running sums would exceed 64 KB
+    int wpb = L.wpb;
+    while (wpb > 1 && (int64_t)wpb * tile3d_lds_bytes(mode, L.TY, 4) > 64 * 1024) wpb /= 2;
+    const int grid = (int)((nt + wpb - 1) / wpb);
     const int kw = p.window[2];
-    if (mode == MODE_U8) return launch_fast3d_modeu8(g, kw, L.TY, vec, grid, L.wpb, s);
-    if (mode == MODE_U16) return launch_fast3d_modeu16(g, kw, L.TY, vec, grid, L.wpb, s);
-    return launch_fast3d_modef64(g, kw, L.TY, vec, grid, L.wpb, s);
+    if (mode == MODE_U8) return launch_fast3d_modeu8(g, kw, L.TY, vec, grid, wpb, s);
+    if (mode == MODE_U16) return launch_fast3d_modeu16(g, kw, L.TY, vec, grid, wpb, s);
+    return launch_fast3d_modef64(g, kw, L.TY, vec, grid, wpb, s);
 }
 
 }  // namespace swc

@@ -69,17 +69,70 @@ __device__ __forceinline__ Col<M> col_delta(T a, T b, T ao, T bo, int m, int mo)
     return d;
 }
 
+// LDS bytes per wave for the running 3-D sums (TY rows x R columns).
+template <int M, int TY> __host__ __device__ constexpr int tile3d_lds_per_wave(int R)
+{
+    return TY * R * (int)sizeof(Col<M>) * kWave;
+}
+__host__ __device__ inline int tile3d_lds_bytes(int mode, int TY, int R)
+{
+    const int cb = mode == MODE_U8 ? (int)sizeof(Col<MODE_U8>)
+                                   : (mode == MODE_U16 ? (int)sizeof(Col<MODE_U16>)
+                                                       : (int)sizeof(Col<MODE_F64>));
+    return TY * R * cb * kWave;
+}
+
+// Running 3-D sums of one (row, column) slot in LDS, one 32-bit word per
+// lane per component, components strided by 64 lanes (conflict-free).
+template <int M> struct S3Slot {
+    uint32_t* base;   // word 0 of this slot for lane 0
+    static constexpr int NDW = (int)(sizeof(Col<M>) / 4);
+    __device__ __forceinline__ void add(int lane, const Col<M>& v) const
+    {
+        uint32_t w[NDW], a[NDW];
+        __builtin_memcpy(a, &v, sizeof(Col<M>));
+#pragma unroll
+        for (int i = 0; i < NDW; i++) w[i] = base[i * kWave + lane];
+        Col<M> cur;
+        __builtin_memcpy(&cur, w, sizeof(Col<M>));
+        col_add<M>(cur, v);
+        __builtin_memcpy(w, &cur, sizeof(Col<M>));
+#pragma unroll
+        for (int i = 0; i < NDW; i++) base[i * kWave + lane] = w[i];
+        (void)a;
+    }
+    __device__ __forceinline__ Col<M> get(int lane) const
+    {
+        uint32_t w[NDW];
+#pragma unroll
+        for (int i = 0; i < NDW; i++) w[i] = base[i * kWave + lane];
+        Col<M> cur;
+        __builtin_memcpy(&cur, w, sizeof(Col<M>));
+        return cur;
+    }
+    __device__ __forceinline__ void zero(int lane) const
+    {
+#pragma unroll
+        for (int i = 0; i < NDW; i++) base[i * kWave + lane] = 0u;
+    }
+};
+
+// One row of entering and leaving raw values per lane.
+template <class T, int R> struct Row3 {
+    static constexpr int NW = Run<T, R>::NW;
+    uint32_t xi[NW], yi[NW], xo[NW], yo[NW];
+};
+
 template <int M, int R, int KW, int TY, bool VEC>
-__device__ __forceinline__ void tile3d(const P3D& g, const int tile)
+__device__ __forceinline__ void tile3d(const P3D& g, const int tile, char* smem)
 {
     using T = typename Tr<M>::T;
     constexpr int LH = KW / 2;
-    constexpr int RH = KW - 1 - LH;
     constexpr int NW = Run<T, R>::NW;
     constexpr bool kFloat = (M == MODE_F64);
     const int lane = threadIdx.x & (kWave - 1);
 
-    // ---- tile geometry: y fastest, then x, then z ----
+    // ---- tile geometry (wave-uniform): y fastest, then x, then z ----
     const int ty = tile % g.tiles_y;
     const int rest = tile / g.tiles_y;
     const int tx = rest % g.tiles_x;
@@ -108,10 +161,11 @@ __device__ __forceinline__ void tile3d(const P3D& g, const int tile)
         colok |= ok ? (1u << j) : 0u;
         cidx[j] = ok ? c : (c < 0 ? 0 : W - 1);
     }
-    const uint32_t lane_boff = VEC ? (uint32_t)((colok & 1u) ? c0 : 0) * (uint32_t)sizeof(T) : 0u;
+    // VEC (W a multiple of R): a lane's run is entirely inside or outside [0, W)
+    const uint32_t lane_vo = (colok & 1u) ? (uint32_t)c0 * (uint32_t)sizeof(T) : kOffNone;
     uint32_t omask = 0, fillb = 0;
     int qj[R];
-    double ncol[R];
+    int ncol[R];
 #pragma unroll
     for (int j = 0; j < R; j++) {
         const int qs = c0 + j - g.ox - LH;
@@ -124,92 +178,113 @@ __device__ __forceinline__ void tile3d(const P3D& g, const int tile)
         qj[j] = q;
         const int clo = q * g.sx + g.ox, chi = clo + KW - 1;
         fillb |= (fill && (clo < 0 || chi >= W)) ? (1u << j) : 0u;
-        ncol[j] = (double)(min(chi, W - 1) - max(clo, 0) + 1);
+        ncol[j] = min(chi, W - 1) - max(clo, 0) + 1;
     }
 
     // ---- rows of the y-windows of this tile's output rows ----
     const int ys = py0 * g.sy + g.oy;               // first window row
     const int nyr = (pyn - 1) * g.sy + g.ky;        // window rows in the tile
-    double nrow[TY];
-    bool rowb[TY];
-#pragma unroll
-    for (int t = 0; t < TY; t++) {
-        const int lo = (py0 + t) * g.sy + g.oy, hi = lo + g.ky - 1;
-        rowb[t] = fill && (lo < 0 || hi >= H);
-        nrow[t] = (double)(min(hi, H - 1) - max(lo, 0) + 1);
-    }
     // ---- planes ----
     const int zs = pz0 * g.sz + g.oz;               // first window plane
     const int nz = (pzn - 1) * g.sz + g.kz;
 
     const char* __restrict__ Xb = (const char*)g.x;
     const char* __restrict__ Yb = (const char*)g.y;
-    const size_t plane = (size_t)H * (size_t)W;
-    auto load = [&](int z, int r, T (&vx)[R], T (&vy)[R]) {
-        const bool ok = z >= 0 && z < D && r >= 0 && r < H;
-        const size_t rb = ok ? ((size_t)z * plane + (size_t)r * W) : 0;
+    const int64_t rowbytes = (int64_t)W * (int64_t)sizeof(T);
+    const int64_t planebytes = (int64_t)H * rowbytes;
+
+    // raw buffer over row r of plane z (zero records outside the volume)
+    auto rsrc = [&](const char* A, int z, int r) {
+        const bool ok = (unsigned)z < (unsigned)D && (unsigned)r < (unsigned)H;
+        const int64_t o = ok ? (int64_t)z * planebytes + (int64_t)r * rowbytes : 0;
+        return __builtin_amdgcn_make_buffer_rsrc((void*)(A + o), (short)0, ok ? (int)rowbytes : 0,
+                                                 kBufWord3);
+    };
+    auto load_row = [&](int zin, int zout, int r, Row3<T, R>& out) __attribute__((always_inline)) {
         if constexpr (VEC) {
-            uint32_t wx[NW], wy[NW];
-            const T* px = (const T*)__builtin_assume_aligned(Xb + rb * sizeof(T) + lane_boff, sizeof(T) * R);
-            const T* py = (const T*)__builtin_assume_aligned(Yb + rb * sizeof(T) + lane_boff, sizeof(T) * R);
-            __builtin_memcpy(wx, px, sizeof(T) * R);
-            __builtin_memcpy(wy, py, sizeof(T) * R);
-            __builtin_memcpy(vx, wx, sizeof(T) * R);
-            __builtin_memcpy(vy, wy, sizeof(T) * R);
+            buf_load_words<NW>(rsrc(Xb, zin, r), lane_vo, out.xi);
+            buf_load_words<NW>(rsrc(Yb, zin, r), lane_vo, out.yi);
+            buf_load_words<NW>(rsrc(Xb, zout, r), lane_vo, out.xo);
+            buf_load_words<NW>(rsrc(Yb, zout, r), lane_vo, out.yo);
         } else {
-            const T* xr = (const T*)g.x + rb;
-            const T* yr = (const T*)g.y + rb;
+            auto one = [&](int z, int rr, uint32_t (&wx)[NW], uint32_t (&wy)[NW]) {
+                const bool ok = (unsigned)z < (unsigned)D && (unsigned)rr < (unsigned)H;
+                const size_t rb = ok ? ((size_t)z * (size_t)H + (size_t)rr) * (size_t)W : 0;
+                const T* xr = (const T*)g.x + rb;
+                const T* yr = (const T*)g.y + rb;
+                T vx[R], vy[R];
 #pragma unroll
-            for (int j = 0; j < R; j++) { vx[j] = xr[cidx[j]]; vy[j] = yr[cidx[j]]; }
-        }
+                for (int j = 0; j < R; j++) {
+                    const bool v = ok && ((colok >> j) & 1u);
+                    vx[j] = v ? xr[cidx[j]] : (T)0;
+                    vy[j] = v ? yr[cidx[j]] : (T)0;
+                }
+                uint32_t tx_[NW] = {}, ty_[NW] = {};
+                __builtin_memcpy(tx_, vx, sizeof(T) * R);
+                __builtin_memcpy(ty_, vy, sizeof(T) * R);
 #pragma unroll
-        for (int j = 0; j < R; j++) {
-            const bool v = ok && (!edge || ((colok >> j) & 1u));
-            vx[j] = v ? vx[j] : (T)0;
-            vy[j] = v ? vy[j] : (T)0;
+                for (int i = 0; i < NW; i++) { wx[i] = tx_[i]; wy[i] = ty_[i]; }
+            };
+            one(zin, r, out.xi, out.yi);
+            one(zout, r, out.xo, out.yo);
         }
     };
 
-    Col<M> S3[TY][R];
+    // running 3-D sums in LDS: slot (t, j) at word offset (t*R + j) * NDW * 64
+    constexpr int NDW = S3Slot<M>::NDW;
+    uint32_t* s3w = (uint32_t*)smem;
+    auto slot = [&](int t, int j) { return S3Slot<M>{s3w + (t * R + j) * NDW * kWave}; };
 #pragma unroll
     for (int t = 0; t < TY; t++)
 #pragma unroll
-        for (int j = 0; j < R; j++) col_zero<M>(S3[t][j]);
+        for (int j = 0; j < R; j++) slot(t, j).zero(lane);
     float hmx = 0.f, hmy = 0.f;
 
     int next_ready = g.kz - 1;
     int pz = pz0;
     for (int li = 0; li < nz; li++) {
         const int zin = zs + li;
-        const int zout = zin - g.kz;
-        const bool has_out = li >= g.kz;
-        // ---- y-window sums of the z-difference field ----
+        const int zout = li >= g.kz ? zin - g.kz : -1;     // -1: nothing leaves yet
+        // ---- y-window sums of the z-difference field (registers) ----
         Col<M> VY[TY][R];
 #pragma unroll
         for (int t = 0; t < TY; t++)
 #pragma unroll
             for (int j = 0; j < R; j++) col_zero<M>(VY[t][j]);
-        for (int r = 0; r < nyr; r++) {
+        auto consume = [&](int r, Row3<T, R>& rw) __attribute__((always_inline)) {
             T ax[R], ay[R], bx[R], by[R];
-            load(zin, ys + r, ax, ay);
-            if (has_out) {
-                load(zout, ys + r, bx, by);
-            } else {
-#pragma unroll
-                for (int j = 0; j < R; j++) { bx[j] = (T)0; by[j] = (T)0; }
-            }
+            __builtin_memcpy(ax, rw.xi, sizeof(T) * R);
+            __builtin_memcpy(ay, rw.yi, sizeof(T) * R);
+            __builtin_memcpy(bx, rw.xo, sizeof(T) * R);
+            __builtin_memcpy(by, rw.yo, sizeof(T) * R);
             int m[R], mo[R];
 #pragma unroll
-            for (int j = 0; j < R; j++) {
-                m[j] = 0;
-                mo[j] = 0;
-                if constexpr (kFloat) {
-                    m[j] = (is_missing(ax[j], g.miss_thr) || is_missing(ay[j], g.miss_thr)) ? 1 : 0;
-                    mo[j] = (is_missing(bx[j], g.miss_thr) || is_missing(by[j], g.miss_thr)) ? 1 : 0;
-                    ax[j] = m[j] ? 0.f : ax[j];
-                    ay[j] = m[j] ? 0.f : ay[j];
-                    bx[j] = mo[j] ? 0.f : bx[j];
-                    by[j] = mo[j] ? 0.f : by[j];
+            for (int j = 0; j < R; j++) { m[j] = 0; mo[j] = 0; }
+            if constexpr (kFloat) {
+                // missing values are rare: test the row's extremes first
+                float lo = ax[0], hi = ax[0];
+                bool nan = false;
+#pragma unroll
+                for (int j = 0; j < R; j++) {
+                    lo = fminf(lo, fminf(fminf(ax[j], ay[j]), fminf(bx[j], by[j])));
+                    hi = fmaxf(hi, fmaxf(fmaxf(ax[j], ay[j]), fmaxf(bx[j], by[j])));
+                    nan = nan | (ax[j] != ax[j]) | (ay[j] != ay[j]) | (bx[j] != bx[j]) |
+                          (by[j] != by[j]);
+                }
+                const bool clean = (lo > g.miss_thr) & (hi < __builtin_inff()) & !nan;
+                if (__builtin_amdgcn_ballot_w64(!clean)) {
+#pragma unroll
+                    for (int j = 0; j < R; j++) {
+                        m[j] = (is_missing(ax[j], g.miss_thr) | is_missing(ay[j], g.miss_thr)) ? 1 : 0;
+                        mo[j] = (is_missing(bx[j], g.miss_thr) | is_missing(by[j], g.miss_thr)) ? 1 : 0;
+                        ax[j] = m[j] ? 0.f : ax[j];
+                        ay[j] = m[j] ? 0.f : ay[j];
+                        bx[j] = mo[j] ? 0.f : bx[j];
+                        by[j] = mo[j] ? 0.f : by[j];
+                    }
+                }
+#pragma unroll
+                for (int j = 0; j < R; j++) {
                     hmx = fmaxf(hmx, __builtin_fabsf(ax[j]));
                     hmy = fmaxf(hmy, __builtin_fabsf(ay[j]));
                 }
@@ -223,23 +298,24 @@ __device__ __forceinline__ void tile3d(const P3D& g, const int tile)
                     if (t < pyn && r >= lo && r < lo + g.ky) col_add<M>(VY[t][j], d);
                 }
             }
+        };
+        // rows in pairs: the next row's loads are in flight while one is used
+        Row3<T, R> A, B;
+        load_row(zin, zout, ys, A);
+        for (int r = 0; r < nyr; r += 2) {
+            if (r + 1 < nyr) load_row(zin, zout, ys + r + 1, B);
+            consume(r, A);
+            if (r + 1 >= nyr) break;
+            if (r + 2 < nyr) load_row(zin, zout, ys + r + 2, A);
+            consume(r + 1, B);
         }
-        // ---- x-window through the halo exchange, accumulated into S3 ----
+        // ---- x-window sums, added to the running 3-D sums ----
 #pragma unroll
         for (int t = 0; t < TY; t++) {
-            Col<M> S, keepL[R > 1 ? R - 1 : 1], keepR[R > 1 ? R - 1 : 1];
-            halo_window<M, R, KW>(VY[t], S, keepL, keepR);
-#pragma unroll
-            for (int j = 0; j < R; j++) {
-                if (j > 0) {
-                    const int ca = j + RH, cs = j - 1 - LH;
-                    const Col<M>& va = ca < R ? VY[t][ca] : keepR[ca - RH - 1];
-                    const Col<M>& vs = cs < 0 ? keepL[cs + LH] : VY[t][cs];
-                    col_add<M>(S, va);
-                    col_sub<M>(S, vs);
-                }
-                col_add<M>(S3[t][j], S);
-            }
+            if (t >= pyn) continue;
+            hsum_row<M, R, KW>(VY[t], [&](int j, const Col<M>& S) __attribute__((always_inline)) {
+                slot(t, j).add(lane, S);
+            });
         }
         if (li != next_ready) continue;
         next_ready += g.sz;
@@ -262,33 +338,32 @@ __device__ __forceinline__ void tile3d(const P3D& g, const int tile)
 #pragma unroll
         for (int t = 0; t < TY; t++) {
             if (t >= pyn) continue;
+            const int ylo = (py0 + t) * g.sy + g.oy, yhi = ylo + g.ky - 1;
+            const bool rowb = fill && (ylo < 0 || yhi >= H);
+            const double nrow = (double)(min(yhi, H - 1) - max(ylo, 0) + 1);
             const size_t orow = ((size_t)pz * g.OH + (size_t)(py0 + t)) * (size_t)g.OW;
 #pragma unroll
             for (int j = 0; j < R; j++) {
                 if (!((omask >> j) & 1u)) continue;
-                const Col<M>& A = S3[t][j];
-                const bool fb = zb || rowb[t] || ((fillb >> j) & 1u);
-                const double dn = nzp * nrow[t] * ncol[j];
+                const Col<M> A3 = slot(t, j).get(lane);
+                const bool fb = zb || rowb || ((fillb >> j) & 1u);
+                const double dn = nzp * nrow * (double)ncol[j];
                 uint8_t fl = 0;
                 float cv = 0.f;
                 if (fb) {
                     fl = FL_BORDER;
                 } else if constexpr (kFloat) {
-                    if (A.miss > 0) {
+                    if (A3.miss > 0) {
                         fl = FL_MISSING;
                     } else {
-                        Acc<MODE_F64> acc;
-                        acc.x = A.x; acc.y = A.y; acc.xx = A.xx; acc.xy = A.xy; acc.yy = A.yy;
-                        acc.miss = 0;
                         const int64_t clo = (int64_t)qj[j] * g.sx + g.ox;
-                        const int64_t ylo = (int64_t)(py0 + t) * g.sy + g.oy;
-                        WinBox wb{(int64_t)plane, (int64_t)W, max(zlo, 0), min(zhi, D - 1),
-                                  max(ylo, (int64_t)0), min(ylo + g.ky - 1, (int64_t)H - 1),
+                        WinBox wb{(int64_t)H * W, (int64_t)W, max(zlo, 0), min(zhi, D - 1),
+                                  max(ylo, 0), min(yhi, H - 1),
                                   max(clo, (int64_t)0), min(clo + KW - 1, (int64_t)W - 1)};
                         // certification against the per-plane thresholds
-                        const double N = __builtin_fma(dn, A.xy, -(A.x * A.y));
-                        const double Vx = __builtin_fma(dn, A.xx, -(A.x * A.x));
-                        const double Vy = __builtin_fma(dn, A.yy, -(A.y * A.y));
+                        const double N = __builtin_fma(dn, A3.xy, -(A3.x * A3.y));
+                        const double Vx = __builtin_fma(dn, A3.xx, -(A3.x * A3.x));
+                        const double Vy = __builtin_fma(dn, A3.yy, -(A3.y * A3.y));
                         const bool cert = (Vx > gx) && (Vy > gy) && !(g.force & 1);
                         if (cert) {
                             cv = clamp_unit(N * rsqrt64(Vx * Vy));
@@ -298,10 +373,10 @@ __device__ __forceinline__ void tile3d(const P3D& g, const int tile)
                         }
                     }
                 } else {
-                    const double sxv = (double)A.x, syv = (double)A.y;
-                    const double N = __builtin_fma(0.5 * dn, (double)A.xy2, -(sxv * syv));
-                    const double Vx = __builtin_fma(dn, (double)A.xx, -(sxv * sxv));
-                    const double Vy = __builtin_fma(dn, (double)A.yy, -(syv * syv));
+                    const double sxv = (double)A3.x, syv = (double)A3.y;
+                    const double N = __builtin_fma(0.5 * dn, (double)A3.xy2, -(sxv * syv));
+                    const double Vx = __builtin_fma(dn, (double)A3.xx, -(sxv * sxv));
+                    const double Vy = __builtin_fma(dn, (double)A3.yy, -(syv * syv));
                     fl = (Vx == 0.0 ? FL_ZVAR_X : 0) | (Vy == 0.0 ? FL_ZVAR_Y : 0);
                     if (!fl) cv = rn32_certified(N, Vx, Vy, (g.force & 1) != 0);
                 }
@@ -318,11 +393,12 @@ template <int M, int R, int KW, int TY, bool VEC>
 __global__ void __launch_bounds__(256)
 __attribute__((amdgpu_waves_per_eu(2, 8))) corr3d_kernel(P3D g)
 {
+    extern __shared__ __attribute__((aligned(16))) char smem[];
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);   // wave-uniform
     const int wpb = blockDim.x / kWave;
     const int tile = xcd_remap(blockIdx.x, gridDim.x) * wpb + wv;
     if (tile >= g.n_tiles) return;
-    tile3d<M, R, KW, TY, VEC>(g, tile);
+    tile3d<M, R, KW, TY, VEC>(g, tile, smem + (size_t)wv * tile3d_lds_per_wave<M, TY>(R));
 }
 
 }  // namespace swc

@@ -7,10 +7,11 @@ namespace swc {
 template <int KW, int TY>
 static hipError_t go3(const P3D& g, bool vec, int grid, int wpb, hipStream_t s)
 {
+    const size_t smem = (size_t)wpb * tile3d_lds_per_wave<MODE_F64, TY>(4);
     if (vec)
-        hipLaunchKernelGGL((corr3d_kernel<MODE_F64, 4, KW, TY, true>), dim3(grid), dim3(wpb * kWave), 0, s, g);
+        hipLaunchKernelGGL((corr3d_kernel<MODE_F64, 4, KW, TY, true>), dim3(grid), dim3(wpb * kWave), smem, s, g);
     else
-        hipLaunchKernelGGL((corr3d_kernel<MODE_F64, 4, KW, TY, false>), dim3(grid), dim3(wpb * kWave), 0, s, g);
+        hipLaunchKernelGGL((corr3d_kernel<MODE_F64, 4, KW, TY, false>), dim3(grid), dim3(wpb * kWave), smem, s, g);
     return hipGetLastError();
 }
 
