@@ -86,12 +86,21 @@ def _kernel_source_hash(workload="c1"):
     h = hashlib.sha256()
     d = os.path.join(ROOT, "paper_1807_06507_amd", "csrc")
     files = [os.path.join(d, f) for f in sorted(_KERNEL_SOURCES[workload])]
-    files += [os.path.join(ROOT, "include", "swcorr.h"),
-              os.path.join(ROOT, "paper_1807_06507_amd", "tune_table.txt")]
+    files += [os.path.join(ROOT, "include", "swcorr.h")]
     for f in files:
         if os.path.exists(f):
             with open(f, "rb") as fh:
                 h.update(os.path.basename(f).encode() + fh.read())
+    # only the tuning-table entries of the workload's dimensionality choose
+    # its launch configuration
+    ndim = 2 if WORKLOADS[workload].get("batched") else len(WORKLOADS[workload]["shape"])
+    tt = os.path.join(ROOT, "paper_1807_06507_amd", "tune_table.txt")
+    if os.path.exists(tt):
+        with open(tt) as fh:
+            for line in fh:
+                f = line.split()
+                if len(f) >= 2 and not line.startswith("#") and f[1] == str(ndim):
+                    h.update(line.strip().encode() + b"\n")
     return h.hexdigest()[:16]
 
 
