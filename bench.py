@@ -184,6 +184,40 @@ def _timed(torch, stream, n, fn):
     return elapsed, np.array([a.elapsed_time(b) for a, b in ev])
 
 
+def unfused_baselines(torch, swc, xd, yd, w, stream, fused_ms, reps=5):
+    """The same map by the two unfused schemes (the paper's four-phase
+    parallel scheme; integral images for integer inputs), timed with HIP
+    events around each whole scheme call, against the fused kernel."""
+    import ctypes
+    res = {"fused_ms": round(fused_ms, 5)}
+    esz = xd.element_size()
+    # one read and one write of every intermediate matrix, inputs, output
+    bytes_px = {"unfused": 2 * esz + 6 * 8 * 2 * 3 + 4, "cumsum": 2 * esz + 5 * 8 * 2 * 2 + 4}
+    for scheme in ("unfused", "cumsum"):
+        if scheme == "cumsum" and xd.dtype == torch.float32:
+            continue
+        p = swc.make_problem(tuple(xd.shape), xd.dtype, w["window"], 1, w["border"])
+        ws = torch.empty(swc.scheme_workspace_bytes(p, scheme), dtype=torch.uint8, device=xd.device)
+        out = torch.empty(swc.output_shape(p), dtype=torch.float32, device=xd.device)
+        lib = swc._load()
+        h = ctypes.c_void_p(int(stream.cuda_stream))
+
+        def run(i):
+            code = lib.swc_corr_scheme(ctypes.byref(p), swc.SCHEMES[scheme],
+                                       ctypes.c_void_p(xd.data_ptr()), ctypes.c_void_p(yd.data_ptr()),
+                                       ctypes.c_void_p(out.data_ptr()), None,
+                                       ctypes.c_void_p(ws.data_ptr()), ctypes.c_uint64(ws.numel()), h)
+            if code != 0:
+                raise RuntimeError(swc.status_str(code))
+        run(0)
+        _, ms = _timed(torch, stream, reps, run)
+        res[f"{scheme}_ms"] = round(float(ms.mean()), 4)
+        res[f"{scheme}_bytes_per_px"] = bytes_px[scheme]
+        res[f"fused_speedup_vs_{scheme}"] = round(float(ms.mean()) / fused_ms, 1)
+        del ws, out
+    return res
+
+
 def run_batched(args, torch, swc, dev):
     """The batched workload: one persistent launch over all 64 pairs, against
     64 per-image launches (eager and captured in one graph)."""
@@ -249,6 +283,8 @@ def main():
     ap.add_argument("--sets", type=int, default=0, help="buffer sets (0 = auto, > 2x MALL)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-copy", action="store_true", help="skip the copy-ceiling probe")
+    ap.add_argument("--no-schemes", action="store_true",
+                    help="skip the unfused baseline schemes (2-D workloads)")
     ap.add_argument("--params", default="", help="R,TH,wpb[,minw,TY] launch parameters")
     args = ap.parse_args()
 
@@ -318,6 +354,9 @@ def main():
         "algorithmic_bytes_per_launch": algo_bytes,
         "kernel_source_hash": khash,
     }
+    if not args.no_schemes and len(w["shape"]) == 2 and tuple(w["step"]) == (1, 1):
+        line["unfused_baselines"] = unfused_baselines(torch, swc, sets[0][0], sets[0][1], w,
+                                                      stream, float(launch_ms.mean()))
     if not args.no_copy:
         line["copy_ceiling_GBps"] = round(copy_ceiling(torch), 1)
     if not args.no_cpu:

@@ -162,6 +162,34 @@ swc_status swc_corr(const swc_problem *p, const void *x, const void *y, float *c
 swc_status swc_corr_ex(const swc_problem *p, const swc_launch_params *lp, const void *x,
                        const void *y, float *c, uint8_t *flags, void *stream);
 
+/* ---- unfused baseline schemes ------------------------------------------ */
+/* The same 2-D map computed by two unfused schemes, kept as measured
+ * baselines for swc_corr:
+ *   SWC_SCHEME_UNFUSED: the paper's parallel scheme (Section 2): element
+ *     products, then one thread per row (step 2) and one thread per column
+ *     (step 3) running moving sums, then the formula per element (step 4),
+ *     with every intermediate matrix of Section 1 stored in the workspace.
+ *   SWC_SCHEME_CUMSUM: the cumulative-sum alternative mentioned at the end
+ *     of Section 1: 2-D prefix sums of the five channels, window sums by
+ *     inclusion-exclusion of four corners.  uint8/uint16 only (exact uint64
+ *     prefix sums).
+ * Results equal swc_corr's (same flags, same certified rounding).  Supported:
+ * ndim 2, step 1, FILL or CLIP, SWC_ACC_DEFAULT; anything else returns
+ * SWC_ERR_UNSUPPORTED. */
+typedef enum swc_scheme { SWC_SCHEME_UNFUSED = 1, SWC_SCHEME_CUMSUM = 2 } swc_scheme;
+/* Workspace bytes the scheme needs for problem p (host only):
+ * UNFUSED 256 + 96 * H * W, CUMSUM 40 * H * W. */
+swc_status swc_scheme_workspace(const swc_problem *p, int32_t scheme, uint64_t *bytes);
+/* Run a scheme on `stream` (asynchronous; several kernels in order).
+ *   x, y, c, flags: as for swc_corr (flags may be NULL)
+ *   workspace: device buffer of at least swc_scheme_workspace() bytes,
+ *     8-byte aligned, owned by the caller, overwritten; it must not be used
+ *     by other work until the stream has finished this call.
+ * Returns SWC_ERR_WORKSPACE when the workspace is too small or misaligned.
+ * Allocates nothing. */
+swc_status swc_corr_scheme(const swc_problem *p, int32_t scheme, const void *x, const void *y,
+                           float *c, uint8_t *flags, void *workspace, uint64_t workspace_bytes,
+                           void *stream);
 /* ---- tuning table ------------------------------------------------------ */
 
 /* Register launch parameters for problems like `p` (same dtype, ndim,

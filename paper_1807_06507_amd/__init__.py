@@ -111,8 +111,11 @@ def _load():
         lib.swc_batch_plan_items.restype = ctypes.c_int64
         lib.swc_batch_plan_destroy.argtypes = [vp]
         lib.swc_batch_plan_destroy.restype = None
+        lib.swc_scheme_workspace.argtypes = [P, ctypes.c_int32, ctypes.POINTER(ctypes.c_uint64)]
+        lib.swc_corr_scheme.argtypes = [P, ctypes.c_int32, vp, vp, vp, vp, vp, ctypes.c_uint64, vp]
         for fn in ("swc_validate", "swc_output_shape", "swc_corr", "swc_corr_ex", "swc_tune_set",
-                   "swc_tune_get", "swc_batch_plan_create", "swc_batch_launch"):
+                   "swc_tune_get", "swc_batch_plan_create", "swc_batch_launch",
+                   "swc_scheme_workspace", "swc_corr_scheme"):
             getattr(lib, fn).restype = ctypes.c_int
         _lib = lib
         return lib
@@ -258,6 +261,50 @@ def corr(x, y, window, step=1, border="fill", invalid=-2.0, missing_le=-999.0,
         if tuple(fl.shape) != oshape or fl.dtype != torch.uint8:
             raise ValueError(f"flags must be uint8 of shape {oshape}")
     corr_into(p, x, y, out, fl, params, stream)
+    return (out, fl) if return_flags else out
+
+
+SCHEMES = {"unfused": 1, "cumsum": 2}
+
+
+def scheme_workspace_bytes(p: Problem, scheme: str) -> int:
+    """Workspace bytes an unfused baseline scheme needs for problem ``p``."""
+    n = ctypes.c_uint64(0)
+    _check(_load().swc_scheme_workspace(ctypes.byref(p), SCHEMES[scheme], ctypes.byref(n)))
+    return int(n.value)
+
+
+def corr_scheme(x, y, window, scheme="unfused", border="fill", invalid=-2.0, missing_le=-999.0,
+                return_flags=False, workspace=None, stream=None):
+    """The same 2-D map by one of the unfused baseline schemes: "unfused"
+    (the paper's four-phase parallel scheme with intermediates in device
+    memory) or "cumsum" (integral images; uint8/uint16).  Step 1 only.
+    ``workspace`` (a uint8 device tensor) is allocated when not given."""
+    import torch
+    _check_tensor(x, "x")
+    _check_tensor(y, "y")
+    if x.shape != y.shape or x.dtype != y.dtype:
+        raise ValueError("x and y must have the same shape and dtype")
+    if scheme not in SCHEMES:
+        raise ValueError(f"scheme must be one of {sorted(SCHEMES)}")
+    p = make_problem(tuple(x.shape), x.dtype, window, 1, border, "default", invalid, missing_le)
+    code = validate(p)
+    if code != 0:
+        raise ValueError(f"{STATUS.get(code)}: {status_str(code)}")
+    nbytes = scheme_workspace_bytes(p, scheme)
+    if workspace is None:
+        workspace = torch.empty(nbytes, dtype=torch.uint8, device=x.device)
+    _check_tensor(workspace, "workspace")
+    oshape = output_shape(p)
+    out = torch.empty(oshape, dtype=torch.float32, device=x.device)
+    fl = torch.empty(oshape, dtype=torch.uint8, device=x.device) if return_flags else None
+    h = _stream_handle(stream, x.device)
+    code = _load().swc_corr_scheme(
+        ctypes.byref(p), SCHEMES[scheme], ctypes.c_void_p(x.data_ptr()),
+        ctypes.c_void_p(y.data_ptr()), ctypes.c_void_p(out.data_ptr()),
+        ctypes.c_void_p(fl.data_ptr()) if fl is not None else None,
+        ctypes.c_void_p(workspace.data_ptr()), ctypes.c_uint64(workspace.numel()), h)
+    _check(code)
     return (out, fl) if return_flags else out
 
 

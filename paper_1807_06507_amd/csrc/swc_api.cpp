@@ -368,4 +368,39 @@ swc_status swc_corr(const swc_problem* p, const void* x, const void* y, float* c
     return swc_corr_ex(p, nullptr, x, y, c, flags, stream);
 }
 
+swc_status swc_scheme_workspace(const swc_problem* p, int32_t scheme, uint64_t* bytes)
+{
+    swc_status st = swc_validate(p);
+    if (st != SWC_OK) return st;
+    if (!bytes) return SWC_ERR_NULL;
+    if (!scheme_supported(*p, scheme)) return SWC_ERR_UNSUPPORTED;
+    *bytes = scheme_workspace_bytes(*p, scheme);
+    return SWC_OK;
+}
+
+swc_status swc_corr_scheme(const swc_problem* p, int32_t scheme, const void* x, const void* y,
+                           float* c, uint8_t* flags, void* workspace, uint64_t workspace_bytes,
+                           void* stream)
+{
+    swc_status st = swc_validate(p);
+    if (st != SWC_OK) return st;
+    if (!x || !y || !c || !workspace) return SWC_ERR_NULL;
+    if (!scheme_supported(*p, scheme)) return SWC_ERR_UNSUPPORTED;
+    if (workspace_bytes < scheme_workspace_bytes(*p, scheme) || ((uintptr_t)workspace % 8) != 0)
+        return SWC_ERR_WORKSPACE;
+    ensure_init();
+    hipError_t pre = hipPeekAtLastError();
+    if (pre != hipSuccess) (void)hipGetLastError();
+    hipError_t e = launch_scheme(*p, scheme, x, y, c, flags, workspace, (hipStream_t)stream,
+                                 g_debug & 1);
+    if (e != hipSuccess) {
+        if (g_log) fprintf(stderr, "[swcorr] scheme launch failed: %s\n", hipGetErrorString(e));
+        return (e == hipErrorInvalidValue || e == hipErrorInvalidConfiguration ||
+                e == hipErrorLaunchFailure)
+                   ? SWC_ERR_LAUNCH
+                   : SWC_ERR_DEVICE;
+    }
+    return SWC_OK;
+}
+
 }  // extern "C"

@@ -42,6 +42,14 @@ hipError_t launch_corr3d(const swc_problem& p, const int64_t* oshape, const Laun
                          const void* x, const void* y, float* c, uint8_t* flags,
                          hipStream_t s, int force);
 
+// Unfused baseline schemes (swc_scheme.hip): support check, workspace size
+// and launch.  The workspace must hold scheme_workspace_bytes() bytes,
+// 8-byte aligned.
+bool scheme_supported(const swc_problem& p, int scheme);
+uint64_t scheme_workspace_bytes(const swc_problem& p, int scheme);
+hipError_t launch_scheme(const swc_problem& p, int scheme, const void* x, const void* y,
+                         float* c, uint8_t* flags, void* ws, hipStream_t s, int force);
+
 // Whether a configuration is launchable for the problem (host check).
 bool cfg_ok_2d(const swc_problem& p, const LaunchCfg& L);
 bool cfg_ok_1d(const swc_problem& p, const LaunchCfg& L);

@@ -28,22 +28,29 @@ def to_dev(a):
 
 
 def gpu_corr(x, y, window, step=1, border="fill", accum="default", params=None,
-             missing_le=-999.0, invalid=-2.0):
+             missing_le=-999.0, invalid=-2.0, scheme=None):
     import torch
     import paper_1807_06507_amd as swc
     xd, yd = to_dev(x), to_dev(y)
-    c, fl = swc.corr(xd, yd, window, step, border, invalid=invalid, missing_le=missing_le,
-                     return_flags=True, accum=accum, params=params)
+    if scheme is not None:
+        assert step in (1, (1, 1)) and accum == "default" and params is None
+        c, fl = swc.corr_scheme(xd, yd, window, scheme, border, invalid=invalid,
+                                missing_le=missing_le, return_flags=True)
+    else:
+        c, fl = swc.corr(xd, yd, window, step, border, invalid=invalid, missing_le=missing_le,
+                         return_flags=True, accum=accum, params=params)
     torch.cuda.synchronize()
     return c.cpu().numpy(), fl.cpu().numpy()
 
 
 def compare(x, y, window, step=1, border="fill", accum="default", params=None, tag="",
-            indices=None, tol=None):
-    """Run both sides, assert parity, return max |dc| over valid outputs."""
+            indices=None, tol=None, scheme=None):
+    """Run both sides, assert parity, return max |dc| over valid outputs.
+    ``scheme`` selects one of the unfused baseline schemes instead of the
+    fused kernels."""
     say(f"[parity] {tag} shape={x.shape} dtype={x.dtype} window={window} step={step} "
-        f"border={border} accum={accum} params={params}")
-    c, fl = gpu_corr(x, y, window, step, border, accum, params)
+        f"border={border} accum={accum} params={params} scheme={scheme}")
+    c, fl = gpu_corr(x, y, window, step, border, accum, params, scheme=scheme)
     if indices is None:
         o32, o64, ofl = oracle.corr(x, y, window, step, border)
         c_cmp, fl_cmp = c, fl

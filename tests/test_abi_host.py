@@ -156,3 +156,29 @@ def test_debug_switch(lib):
     swc.set_debug(1)
     assert swc.get_debug() == 1
     swc.set_debug(old)
+
+
+def test_scheme_workspace_sizes_and_errors(lib):
+    """Host-only: workspace sizes follow the header, unsupported requests and
+    bad workspaces are rejected before any device work."""
+    p = swc.make_problem((300, 400), "uint16", (7, 7), 1, "fill")
+    assert swc.scheme_workspace_bytes(p, "unfused") == 256 + 96 * 300 * 400
+    assert swc.scheme_workspace_bytes(p, "cumsum") == 40 * 300 * 400
+    n = ctypes.c_uint64(0)
+    pf = swc.make_problem((300, 400), "float32", (7, 7), 1, "clip")
+    assert lib.swc_scheme_workspace(ctypes.byref(pf), 2, ctypes.byref(n)) == 12   # cumsum f32
+    assert lib.swc_scheme_workspace(ctypes.byref(pf), 1, ctypes.byref(n)) == 0
+    assert lib.swc_scheme_workspace(ctypes.byref(pf), 3, ctypes.byref(n)) == 12   # no such scheme
+    ps = swc.make_problem((300, 400), "float32", (7, 7), 2, "clip")
+    assert lib.swc_scheme_workspace(ctypes.byref(ps), 1, ctypes.byref(n)) == 12   # step 2
+    pv = swc.make_problem((300, 400), "float32", (7, 7), 1, "valid")
+    assert lib.swc_scheme_workspace(ctypes.byref(pv), 1, ctypes.byref(n)) == 12
+    p3 = swc.make_problem((30, 40, 50), "uint8", (3, 3, 3), 1, "fill")
+    assert lib.swc_scheme_workspace(ctypes.byref(p3), 1, ctypes.byref(n)) == 12
+    # fake (never dereferenced) device addresses: validation fails first
+    fake = ctypes.c_void_p(0x1000)
+    assert lib.swc_corr_scheme(ctypes.byref(p), 1, fake, fake, fake, None, None, 0, None) == 1
+    assert lib.swc_corr_scheme(ctypes.byref(p), 1, fake, fake, fake, None, fake, 100, None) == 9
+    need = swc.scheme_workspace_bytes(p, "unfused")
+    assert lib.swc_corr_scheme(ctypes.byref(p), 1, fake, fake, fake, None,
+                               ctypes.c_void_p(0x1004), need, None) == 9   # misaligned
