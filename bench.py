@@ -218,6 +218,33 @@ def unfused_baselines(torch, swc, xd, yd, w, stream, fused_ms, reps=5):
     return res
 
 
+def host_pipeline(torch, swc, x, y, w, reps=5):
+    """End-to-end host-to-host time (pinned host buffers; copies in and out
+    included, overlapped with the kernels over several streams), best over a
+    few slab heights.  A PCIe-inclusive figure, reported beside `value`."""
+    xt = torch.from_numpy(x).pin_memory()
+    yt = torch.from_numpy(y).pin_memory()
+    best, tried = None, {}
+    rows = x.shape[0]
+    for band in sorted({max(1, rows // 12), max(1, rows // 6), max(1, rows // 3)}):
+        plan = swc.HostPlan(x.shape, x.dtype, w["window"], w["step"], w["border"],
+                            band_rows=band, depth=3)
+        out = torch.empty(plan.oshape, dtype=torch.float32, pin_memory=True)
+        plan.run(xt, yt, out)
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            plan.run(xt, yt, out)
+        ms = (time.perf_counter() - t0) / reps * 1e3
+        tried[band] = round(ms, 3)
+        if best is None or ms < best[1]:
+            best = (band, ms, plan.bands)
+        plan.close()
+    pcie = x.nbytes + y.nbytes + int(np.prod(out.shape)) * 4
+    return {"ms": round(best[1], 3), "gpix_s": round(x.size / (best[1] * 1e-3) / 1e9, 3),
+            "band_rows": best[0], "slabs": best[2], "depth": 3, "pcie_bytes": pcie,
+            "ms_by_band_rows": tried}
+
+
 def run_batched(args, torch, swc, dev):
     """The batched workload: one persistent launch over all 64 pairs, against
     64 per-image launches (eager and captured in one graph)."""
@@ -284,7 +311,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-copy", action="store_true", help="skip the copy-ceiling probe")
     ap.add_argument("--no-schemes", action="store_true",
-                    help="skip the unfused baseline schemes (2-D workloads)")
+                    help="skip the unfused baseline schemes and the host-pipeline run")
     ap.add_argument("--params", default="", help="R,TH,wpb[,minw,TY] launch parameters")
     args = ap.parse_args()
 
@@ -357,6 +384,8 @@ def main():
     if not args.no_schemes and len(w["shape"]) == 2 and tuple(w["step"]) == (1, 1):
         line["unfused_baselines"] = unfused_baselines(torch, swc, sets[0][0], sets[0][1], w,
                                                       stream, float(launch_ms.mean()))
+    if not args.no_schemes and tuple(w["step"])[0] == 1:
+        line["host_pipeline"] = host_pipeline(torch, swc, x, y, w)
     if not args.no_copy:
         line["copy_ceiling_GBps"] = round(copy_ceiling(torch), 1)
     if not args.no_cpu:

@@ -190,6 +190,34 @@ swc_status swc_scheme_workspace(const swc_problem *p, int32_t scheme, uint64_t *
 swc_status swc_corr_scheme(const swc_problem *p, int32_t scheme, const void *x, const void *y,
                            float *c, uint8_t *flags, void *workspace, uint64_t workspace_bytes,
                            void *stream);
+/* ---- end-to-end runs from host memory ---------------------------------- */
+/* A plan for host-to-host runs of problem p (any ndim, step[0] == 1): the
+ * input is cut into slabs of `band_rows` outputs along the first axis (plus
+ * the k-1 halo rows their windows need), and each slab's host-to-device
+ * copies, fused kernel (swc_corr) and device-to-host copy are issued in
+ * order on one of `depth` streams (1..8), so transfers of one slab overlap
+ * the kernel of another.  This is the end-to-end setting of the paper's GPU
+ * timing (Section 3: the time includes the transfers to and from the
+ * device).  Creation allocates `depth` device staging sets and streams (the
+ * plan owns them); returns SWC_ERR_UNSUPPORTED for step[0] != 1,
+ * SWC_ERR_PARAM for band_rows < 1 or depth outside 1..8, SWC_ERR_DEVICE
+ * when allocation fails. */
+typedef struct swc_host_plan swc_host_plan;
+swc_status swc_host_plan_create(const swc_problem *p, int64_t band_rows, int32_t depth,
+                                swc_host_plan **out);
+/* Run the plan: x, y are HOST arrays of p->shape; c (float32) and flags
+ * (uint8, may be NULL) HOST arrays of swc_output_shape(p).  Page-locked
+ * host memory (hipHostMalloc) is needed for the copies to overlap; pageable
+ * memory works but serialises them.  Synchronous: returns once c and flags
+ * hold the result (all streams drained, also after an error).  Results equal
+ * swc_corr's on the whole array (bit-exact for integer input; float input
+ * within the same bound, since the slabs are tiled differently). */
+swc_status swc_host_run(swc_host_plan *plan, const void *x, const void *y, float *c,
+                        uint8_t *flags);
+/* Number of slabs per run. */
+int64_t swc_host_plan_bands(const swc_host_plan *plan);
+/* Free the plan's device memory and streams (NULL is ignored). */
+void swc_host_plan_destroy(swc_host_plan *plan);
 /* ---- tuning table ------------------------------------------------------ */
 
 /* Register launch parameters for problems like `p` (same dtype, ndim,

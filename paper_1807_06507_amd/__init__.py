@@ -19,6 +19,7 @@ __all__ = [
     "Problem", "LaunchParams", "corr", "corr_into", "output_shape", "validate", "status_str",
     "tune_set", "tune_get", "set_debug", "get_debug", "BatchPlan", "library_path",
     "SwcError", "FLAG_BORDER", "FLAG_MISSING", "FLAG_ZVAR_X", "FLAG_ZVAR_Y",
+    "HostPlan", "corr_scheme", "scheme_workspace_bytes", "SCHEMES",
 ]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -113,6 +114,14 @@ def _load():
         lib.swc_batch_plan_destroy.restype = None
         lib.swc_scheme_workspace.argtypes = [P, ctypes.c_int32, ctypes.POINTER(ctypes.c_uint64)]
         lib.swc_corr_scheme.argtypes = [P, ctypes.c_int32, vp, vp, vp, vp, vp, ctypes.c_uint64, vp]
+        lib.swc_host_plan_create.argtypes = [P, ctypes.c_int64, ctypes.c_int32, ctypes.POINTER(vp)]
+        lib.swc_host_run.argtypes = [vp, vp, vp, vp, vp]
+        lib.swc_host_plan_bands.argtypes = [vp]
+        lib.swc_host_plan_bands.restype = ctypes.c_int64
+        lib.swc_host_plan_destroy.argtypes = [vp]
+        lib.swc_host_plan_destroy.restype = None
+        for fn in ("swc_host_plan_create", "swc_host_run"):
+            getattr(lib, fn).restype = ctypes.c_int
         for fn in ("swc_validate", "swc_output_shape", "swc_corr", "swc_corr_ex", "swc_tune_set",
                    "swc_tune_get", "swc_batch_plan_create", "swc_batch_launch",
                    "swc_scheme_workspace", "swc_corr_scheme"):
@@ -306,6 +315,68 @@ def corr_scheme(x, y, window, scheme="unfused", border="fill", invalid=-2.0, mis
         ctypes.c_void_p(workspace.data_ptr()), ctypes.c_uint64(workspace.numel()), h)
     _check(code)
     return (out, fl) if return_flags else out
+
+
+class HostPlan:
+    """End-to-end runs from host memory: slabs along the first axis, each
+    copied in, computed and copied out on one of ``depth`` streams.  Inputs
+    and outputs are CPU tensors (pinned for overlap); the plan owns its
+    device staging buffers."""
+
+    def __init__(self, shape, dtype, window, step=1, border="fill", band_rows=512, depth=3,
+                 invalid=-2.0, missing_le=-999.0):
+        self.problem = make_problem(tuple(shape), dtype, window, step, border, "default",
+                                    invalid, missing_le)
+        code = validate(self.problem)
+        if code != 0:
+            raise ValueError(f"{STATUS.get(code)}: {status_str(code)}")
+        self.oshape = output_shape(self.problem)
+        self._lib = _load()
+        h = ctypes.c_void_p()
+        _check(self._lib.swc_host_plan_create(ctypes.byref(self.problem), int(band_rows),
+                                              int(depth), ctypes.byref(h)))
+        self._h = h
+
+    @property
+    def bands(self) -> int:
+        return int(self._lib.swc_host_plan_bands(self._h))
+
+    def run(self, x, y, out=None, flags=None):
+        """x, y: contiguous CPU tensors of the plan's shape and dtype.
+        Returns (c, flags) CPU tensors (flags None unless given)."""
+        import torch
+        for t, n in ((x, "x"), (y, "y")):
+            if not isinstance(t, torch.Tensor) or t.is_cuda or not t.is_contiguous():
+                raise ValueError(f"{n} must be a contiguous CPU tensor")
+            if tuple(t.shape) != tuple(self.problem.shape[:self.problem.ndim]):
+                raise ValueError(f"{n} has the wrong shape")
+            if _dtype_code(t.dtype) != self.problem.dtype:
+                raise ValueError(f"{n} has the wrong dtype")
+        if out is None:
+            out = torch.empty(self.oshape, dtype=torch.float32, pin_memory=x.is_pinned())
+        if tuple(out.shape) != self.oshape or out.dtype != torch.float32 or out.is_cuda \
+                or not out.is_contiguous():
+            raise ValueError("out must be a contiguous float32 CPU tensor of the output shape")
+        if flags is not None and (tuple(flags.shape) != self.oshape or flags.dtype != torch.uint8
+                                  or flags.is_cuda or not flags.is_contiguous()):
+            raise ValueError("flags must be a contiguous uint8 CPU tensor of the output shape")
+        code = self._lib.swc_host_run(
+            self._h, ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(y.data_ptr()),
+            ctypes.c_void_p(out.data_ptr()),
+            ctypes.c_void_p(flags.data_ptr()) if flags is not None else None)
+        _check(code)
+        return out, flags
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.swc_host_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def tune_set(p: Problem, params) -> None:

@@ -182,3 +182,18 @@ def test_scheme_workspace_sizes_and_errors(lib):
     need = swc.scheme_workspace_bytes(p, "unfused")
     assert lib.swc_corr_scheme(ctypes.byref(p), 1, fake, fake, fake, None,
                                ctypes.c_void_p(0x1004), need, None) == 9   # misaligned
+
+
+def test_host_plan_argument_errors(lib):
+    """Host-only: bad plan arguments are rejected before any device work."""
+    p = swc.make_problem((300, 400), "uint16", (7, 7), (2, 1), "fill")
+    h = ctypes.c_void_p()
+    assert lib.swc_host_plan_create(ctypes.byref(p), 16, 2, ctypes.byref(h)) == 12
+    p = swc.make_problem((300, 400), "uint16", (7, 7), 1, "fill")
+    assert lib.swc_host_plan_create(ctypes.byref(p), 0, 2, ctypes.byref(h)) == 13
+    assert lib.swc_host_plan_create(ctypes.byref(p), 16, 0, ctypes.byref(h)) == 13
+    assert lib.swc_host_plan_create(ctypes.byref(p), 16, 9, ctypes.byref(h)) == 13
+    assert lib.swc_host_plan_create(ctypes.byref(p), 16, 2, None) == 1
+    assert lib.swc_host_run(None, None, None, None, None) == 1
+    assert lib.swc_host_plan_bands(None) == 0
+    lib.swc_host_plan_destroy(None)
