@@ -386,6 +386,15 @@ def main():
                                                       stream, float(launch_ms.mean()))
     if not args.no_schemes and tuple(w["step"])[0] == 1:
         line["host_pipeline"] = host_pipeline(torch, swc, x, y, w)
+    if not args.no_schemes:
+        # the application step on the finished map: cloud mask c < -0.5
+        cmap = sets[0][2]
+        mask = torch.empty(cmap.shape, dtype=torch.uint8, device=dev)
+        swc.cloud_mask(cmap, None, 0.5, out=mask, stream=stream)
+        _, mms = _timed(torch, stream, 20, lambda i: swc.cloud_mask(cmap, None, 0.5, out=mask,
+                                                                     stream=stream))
+        line["cloud_mask"] = {"us": round(float(mms.mean()) * 1e3, 2),
+                              "GBps": round(cmap.numel() * 5 / (float(mms.mean()) * 1e-3) / 1e9, 1)}
     if not args.no_copy:
         line["copy_ceiling_GBps"] = round(copy_ceiling(torch), 1)
     if not args.no_cpu:

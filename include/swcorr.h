@@ -218,6 +218,26 @@ swc_status swc_host_run(swc_host_plan *plan, const void *x, const void *y, float
 int64_t swc_host_plan_bands(const swc_host_plan *plan);
 /* Free the plan's device memory and streams (NULL is ignored). */
 void swc_host_plan_destroy(swc_host_plan *plan);
+/* ---- the application's use of the map ---------------------------------- */
+/* Night-time light detections are false where moonlight is reflected by
+ * clouds; there the visible/infrared correlation is close to -1
+ * (Introduction, Conclusion).  Both calls read a finished map c (device,
+ * float32, n outputs) and its flag map (device uint8, or NULL: then an output
+ * is valid when c differs from invalid_value).  Asynchronous on `stream`,
+ * allocate nothing; n == 0 / k == 0 launch nothing.  Errors: SWC_ERR_SHAPE
+ * for n < 0 or k < 0, SWC_ERR_PARAM for a NaN tau, SWC_ERR_NULL for missing
+ * pointers.
+ * Cloud mask: mask[i] (device uint8, n) = 1 when output i is valid and
+ * c[i] < -tau (float32 comparison), else 0. */
+swc_status swc_cloud_mask(const float *c, const uint8_t *flags, int64_t n, float tau,
+                          float invalid_value, uint8_t *mask, void *stream);
+/* Detection filter: for k detections at flat output indices idx[j] (device
+ * int64), keep[j] (device uint8) = 0 when the detection sits on a cloud
+ * pixel (as in the mask), 1 when it is kept, 2 when idx[j] is outside
+ * [0, n) (checked on the device; nothing outside the map is read). */
+swc_status swc_filter_detections(const float *c, const uint8_t *flags, int64_t n,
+                                 const int64_t *idx, int64_t k, float tau, float invalid_value,
+                                 uint8_t *keep, void *stream);
 /* ---- tuning table ------------------------------------------------------ */
 
 /* Register launch parameters for problems like `p` (same dtype, ndim,

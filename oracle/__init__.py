@@ -147,3 +147,12 @@ def rn32_ratio(P: int, Q: int, R: int, lib=None) -> np.float32:
 
 def has_openmp() -> bool:
     return bool(_load().oracle_has_openmp())
+
+
+def cloud_mask(c32, flags, tau):
+    """The application's cloud test on a finished map (the paper's
+    Introduction: under clouds the visible/infrared correlation is close to
+    -1): 1 where the output is valid (flag 0) and c < -tau, compared in
+    float32, else 0."""
+    c32 = np.asarray(c32, dtype=np.float32)
+    return ((np.asarray(flags) == 0) & (c32 < np.float32(-tau))).astype(np.uint8)

@@ -19,7 +19,8 @@ __all__ = [
     "Problem", "LaunchParams", "corr", "corr_into", "output_shape", "validate", "status_str",
     "tune_set", "tune_get", "set_debug", "get_debug", "BatchPlan", "library_path",
     "SwcError", "FLAG_BORDER", "FLAG_MISSING", "FLAG_ZVAR_X", "FLAG_ZVAR_Y",
-    "HostPlan", "corr_scheme", "scheme_workspace_bytes", "SCHEMES",
+    "HostPlan", "corr_scheme", "scheme_workspace_bytes", "SCHEMES", "cloud_mask",
+    "filter_detections",
 ]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -120,7 +121,12 @@ def _load():
         lib.swc_host_plan_bands.restype = ctypes.c_int64
         lib.swc_host_plan_destroy.argtypes = [vp]
         lib.swc_host_plan_destroy.restype = None
-        for fn in ("swc_host_plan_create", "swc_host_run"):
+        lib.swc_cloud_mask.argtypes = [vp, vp, ctypes.c_int64, ctypes.c_float, ctypes.c_float,
+                                       vp, vp]
+        lib.swc_filter_detections.argtypes = [vp, vp, ctypes.c_int64, vp, ctypes.c_int64,
+                                              ctypes.c_float, ctypes.c_float, vp, vp]
+        for fn in ("swc_host_plan_create", "swc_host_run", "swc_cloud_mask",
+                   "swc_filter_detections"):
             getattr(lib, fn).restype = ctypes.c_int
         for fn in ("swc_validate", "swc_output_shape", "swc_corr", "swc_corr_ex", "swc_tune_set",
                    "swc_tune_get", "swc_batch_plan_create", "swc_batch_launch",
@@ -377,6 +383,51 @@ class HostPlan:
             self.close()
         except Exception:
             pass
+
+
+def cloud_mask(c, flags=None, tau=0.5, invalid=-2.0, out=None, stream=None):
+    """uint8 device mask of the valid outputs with c < -tau (the cloud test of
+    the paper's application)."""
+    import torch
+    _check_tensor(c, "c")
+    if c.dtype != torch.float32:
+        raise ValueError("c must be float32")
+    if flags is not None:
+        _check_tensor(flags, "flags")
+        if flags.shape != c.shape or flags.dtype != torch.uint8:
+            raise ValueError("flags must be uint8 of c's shape")
+    if out is None:
+        out = torch.empty(c.shape, dtype=torch.uint8, device=c.device)
+    _check_tensor(out, "out")
+    if out.shape != c.shape or out.dtype != torch.uint8:
+        raise ValueError("out must be uint8 of c's shape")
+    h = _stream_handle(stream, c.device)
+    _check(_load().swc_cloud_mask(ctypes.c_void_p(c.data_ptr()),
+                                  ctypes.c_void_p(flags.data_ptr()) if flags is not None else None,
+                                  c.numel(), float(tau), float(invalid),
+                                  ctypes.c_void_p(out.data_ptr()), h))
+    return out
+
+
+def filter_detections(c, idx, flags=None, tau=0.5, invalid=-2.0, stream=None):
+    """For detections at flat output indices ``idx`` (int64 device tensor):
+    0 = on a cloud pixel (reject), 1 = keep, 2 = index outside the map."""
+    import torch
+    _check_tensor(c, "c")
+    _check_tensor(idx, "idx")
+    if c.dtype != torch.float32 or idx.dtype != torch.int64:
+        raise ValueError("c must be float32 and idx int64")
+    if flags is not None:
+        _check_tensor(flags, "flags")
+        if flags.shape != c.shape or flags.dtype != torch.uint8:
+            raise ValueError("flags must be uint8 of c's shape")
+    keep = torch.empty(idx.shape, dtype=torch.uint8, device=c.device)
+    h = _stream_handle(stream, c.device)
+    _check(_load().swc_filter_detections(
+        ctypes.c_void_p(c.data_ptr()), ctypes.c_void_p(flags.data_ptr()) if flags is not None else None,
+        c.numel(), ctypes.c_void_p(idx.data_ptr()), idx.numel(), float(tau), float(invalid),
+        ctypes.c_void_p(keep.data_ptr()), h))
+    return keep
 
 
 def tune_set(p: Problem, params) -> None:

@@ -368,6 +368,30 @@ swc_status swc_corr(const swc_problem* p, const void* x, const void* y, float* c
     return swc_corr_ex(p, nullptr, x, y, c, flags, stream);
 }
 
+swc_status swc_cloud_mask(const float* c, const uint8_t* flags, int64_t n, float tau,
+                          float invalid_value, uint8_t* mask, void* stream)
+{
+    if (n < 0) return SWC_ERR_SHAPE;
+    if (isnan(tau)) return SWC_ERR_PARAM;
+    if (n == 0) return SWC_OK;
+    if (!c || !mask) return SWC_ERR_NULL;
+    hipError_t e = launch_cloud_mask(c, flags, n, tau, invalid_value, mask, (hipStream_t)stream);
+    return e == hipSuccess ? SWC_OK : SWC_ERR_LAUNCH;
+}
+
+swc_status swc_filter_detections(const float* c, const uint8_t* flags, int64_t n,
+                                 const int64_t* idx, int64_t k, float tau, float invalid_value,
+                                 uint8_t* keep, void* stream)
+{
+    if (n < 0 || k < 0) return SWC_ERR_SHAPE;
+    if (isnan(tau)) return SWC_ERR_PARAM;
+    if (k == 0) return SWC_OK;
+    if (!idx || !keep || (n > 0 && !c)) return SWC_ERR_NULL;
+    hipError_t e = launch_filter_detections(c, flags, n, idx, k, tau, invalid_value, keep,
+                                            (hipStream_t)stream);
+    return e == hipSuccess ? SWC_OK : SWC_ERR_LAUNCH;
+}
+
 swc_status swc_scheme_workspace(const swc_problem* p, int32_t scheme, uint64_t* bytes)
 {
     swc_status st = swc_validate(p);

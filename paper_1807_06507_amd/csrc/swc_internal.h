@@ -50,6 +50,13 @@ uint64_t scheme_workspace_bytes(const swc_problem& p, int scheme);
 hipError_t launch_scheme(const swc_problem& p, int scheme, const void* x, const void* y,
                          float* c, uint8_t* flags, void* ws, hipStream_t s, int force);
 
+// Application kernels on a finished map (swc_mask.hip).
+hipError_t launch_cloud_mask(const float* c, const uint8_t* flags, int64_t n, float tau,
+                             float invalid, uint8_t* mask, hipStream_t s);
+hipError_t launch_filter_detections(const float* c, const uint8_t* flags, int64_t n,
+                                    const int64_t* idx, int64_t k, float tau, float invalid,
+                                    uint8_t* keep, hipStream_t s);
+
 // Whether a configuration is launchable for the problem (host check).
 bool cfg_ok_2d(const swc_problem& p, const LaunchCfg& L);
 bool cfg_ok_1d(const swc_problem& p, const LaunchCfg& L);

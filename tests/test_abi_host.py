@@ -197,3 +197,15 @@ def test_host_plan_argument_errors(lib):
     assert lib.swc_host_run(None, None, None, None, None) == 1
     assert lib.swc_host_plan_bands(None) == 0
     lib.swc_host_plan_destroy(None)
+
+
+def test_mask_argument_errors(lib):
+    """Host-only: argument errors of the application calls (no device work)."""
+    fake = ctypes.c_void_p(0x1000)
+    assert lib.swc_cloud_mask(fake, None, -1, 0.5, -2.0, fake, None) == 3
+    assert lib.swc_cloud_mask(fake, None, 10, float("nan"), -2.0, fake, None) == 13
+    assert lib.swc_cloud_mask(None, None, 10, 0.5, -2.0, fake, None) == 1
+    assert lib.swc_cloud_mask(None, None, 0, 0.5, -2.0, None, None) == 0
+    assert lib.swc_filter_detections(fake, None, 10, fake, -1, 0.5, -2.0, fake, None) == 3
+    assert lib.swc_filter_detections(fake, None, 10, None, 5, 0.5, -2.0, fake, None) == 1
+    assert lib.swc_filter_detections(None, None, 10, None, 0, 0.5, -2.0, None, None) == 0

@@ -354,3 +354,32 @@ def test_golden_hand_cases():
                 assert c32.ravel()[i].view(np.uint32) == want32.view(np.uint32), (case["name"], i)
             else:
                 assert abs(float(c32.ravel()[i]) - want64) <= np.spacing(np.float32(abs(want64)))
+
+
+def test_cloud_mask_pins():
+    """The application's cloud test (Introduction: under clouds the visible
+    and infrared channels move in opposite directions, c close to -1):
+    an exactly anti-linear patch gives c = -1 and is masked for every
+    tau < 1, never for tau = 1; a co-linear patch is never masked; border
+    outputs (FILL) and constant windows are never masked."""
+    rng = np.random.default_rng(41)
+    x = rng.integers(100, 2000, size=(40, 60)).astype(np.uint16)
+    y = rng.integers(100, 2000, size=(40, 60)).astype(np.uint16)
+    x[5:25, 10:30] = rng.integers(1000, 5000, size=(20, 20))
+    y[5:25, 10:30] = (30000 - 3 * x[5:25, 10:30].astype(np.int64)).astype(np.uint16)
+    x[5:25, 35:55] = rng.integers(1000, 5000, size=(20, 20))
+    y[5:25, 35:55] = (7 + 2 * x[5:25, 35:55].astype(np.int64)).astype(np.uint16)
+    y[30:38, 0:20] = 4444                                   # constant y patch
+    c32, _, fl = oracle.corr(x, y, (5, 5), 1, "fill")
+    inner_anti = (slice(7, 23), slice(12, 28))              # windows inside the patch
+    inner_co = (slice(7, 23), slice(37, 53))
+    assert np.all(c32[inner_anti] == np.float32(-1.0))
+    assert np.all(c32[inner_co] == np.float32(1.0))
+    for tau in (0.0, 0.5, 0.9, 0.999):
+        m = oracle.cloud_mask(c32, fl, tau)
+        assert np.all(m[inner_anti] == 1)
+        assert np.all(m[inner_co] == 0)
+        assert np.all(m[fl != 0] == 0)
+        assert np.all(m[:2, :] == 0) and np.all(m[:, -2:] == 0)
+    assert np.all(oracle.cloud_mask(c32, fl, 1.0) == 0)
+    assert np.all(fl[32:36, 2:18] & oracle.FLAG_ZVAR_Y)
