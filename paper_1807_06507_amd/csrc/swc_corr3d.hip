@@ -78,9 +78,13 @@ hipError_t launch_corr3d(const swc_problem& p, const int64_t* oshape, const Laun
     while (wpb > 1 && (int64_t)wpb * tile3d_lds_bytes(mode, L.TY, 4) > 64 * 1024) wpb /= 2;
     const int grid = (int)((nt + wpb - 1) / wpb);
     const int kw = p.window[2];
-    if (mode == MODE_U8) return launch_fast3d_modeu8(g, kw, L.TY, vec, grid, wpb, s);
-    if (mode == MODE_U16) return launch_fast3d_modeu16(g, kw, L.TY, vec, grid, wpb, s);
-    return launch_fast3d_modef64(g, kw, L.TY, vec, grid, wpb, s);
+    // specialised step: square (y, x) window, unit y step, two rows per wave,
+    // vector loads, every plane addressable with 30-bit offsets
+    const bool cube = vec && L.TY == 2 && p.window[1] == kw && p.step[1] == 1 &&
+                      (int64_t)g.H * g.W * (int64_t)esz < ((int64_t)1 << 30) && !(force & 2);
+    if (mode == MODE_U8) return launch_fast3d_modeu8(g, kw, L.TY, vec, cube, grid, wpb, s);
+    if (mode == MODE_U16) return launch_fast3d_modeu16(g, kw, L.TY, vec, cube, grid, wpb, s);
+    return launch_fast3d_modef64(g, kw, L.TY, vec, cube, grid, wpb, s);
 }
 
 }  // namespace swc

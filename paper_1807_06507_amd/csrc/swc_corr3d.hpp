@@ -16,6 +16,9 @@
 // the same time and march z in step (their shared rows hit the same L2).
 #pragma once
 
+#include <stddef.h>
+#include <type_traits>
+
 #include "swc_corr2d_fast.hpp"
 
 namespace swc {
@@ -41,12 +44,14 @@ __host__ __device__ inline bool fast3d_supported(int mode, int KW)
     return KW == 3 || KW == 5 || KW == 7 || KW == 9;
 }
 
-hipError_t launch_fast3d_modeu8(const P3D& g, int KW, int TY, bool vec, int grid, int wpb,
-                                hipStream_t s);
-hipError_t launch_fast3d_modeu16(const P3D& g, int KW, int TY, bool vec, int grid, int wpb,
-                                 hipStream_t s);
-hipError_t launch_fast3d_modef64(const P3D& g, int KW, int TY, bool vec, int grid, int wpb,
-                                 hipStream_t s);
+// `cube`: use the specialised step (k_y == k_x, unit y step, TY == 2, vector
+// loads, planes below 2^30 bytes); the host checks those conditions.
+hipError_t launch_fast3d_modeu8(const P3D& g, int KW, int TY, bool vec, bool cube, int grid,
+                                int wpb, hipStream_t s);
+hipError_t launch_fast3d_modeu16(const P3D& g, int KW, int TY, bool vec, bool cube, int grid,
+                                 int wpb, hipStream_t s);
+hipError_t launch_fast3d_modef64(const P3D& g, int KW, int TY, bool vec, bool cube, int grid,
+                                 int wpb, hipStream_t s);
 
 // Contribution difference (entering minus leaving) of one element pair, in
 // the running-sum representation of Col<M> (integer modes keep 2*Sxy).
@@ -101,6 +106,20 @@ template <int M> struct S3Slot {
         for (int i = 0; i < NDW; i++) base[i * kWave + lane] = w[i];
         (void)a;
     }
+    // add v and return the new running sum
+    __device__ __forceinline__ Col<M> add_get(int lane, const Col<M>& v) const
+    {
+        uint32_t w[NDW];
+#pragma unroll
+        for (int i = 0; i < NDW; i++) w[i] = base[i * kWave + lane];
+        Col<M> cur;
+        __builtin_memcpy(&cur, w, sizeof(Col<M>));
+        col_add<M>(cur, v);
+        __builtin_memcpy(w, &cur, sizeof(Col<M>));
+#pragma unroll
+        for (int i = 0; i < NDW; i++) base[i * kWave + lane] = w[i];
+        return cur;
+    }
     __device__ __forceinline__ Col<M> get(int lane) const
     {
         uint32_t w[NDW];
@@ -116,6 +135,72 @@ template <int M> struct S3Slot {
         for (int i = 0; i < NDW; i++) base[i * kWave + lane] = 0u;
     }
 };
+
+// Fields of Col<M> one at a time: F-th field by reference, its 32-bit word
+// offset in the struct, and the field count (the missing count is last).
+template <int M> constexpr int col_nfields() { return M == MODE_F64 ? 6 : 5; }
+template <int M, int F> __device__ __forceinline__ auto& col_field(Col<M>& c)
+{
+    if constexpr (M == MODE_F64) {
+        if constexpr (F == 0) return c.x;
+        else if constexpr (F == 1) return c.y;
+        else if constexpr (F == 2) return c.xx;
+        else if constexpr (F == 3) return c.yy;
+        else if constexpr (F == 4) return c.xy;
+        else return c.miss;
+    } else {
+        if constexpr (F == 0) return c.x;
+        else if constexpr (F == 1) return c.y;
+        else if constexpr (F == 2) return c.xx;
+        else if constexpr (F == 3) return c.yy;
+        else return c.xy2;
+    }
+}
+template <int M, int F> constexpr int col_field_word()
+{
+    if constexpr (M == MODE_F64) return F < 5 ? 2 * F : 10;
+    else if constexpr (M == MODE_U16) return F < 2 ? F : 2 + 2 * (F - 2);
+    else return F;
+}
+static_assert(offsetof(Col<MODE_F64>, miss) == 40 && offsetof(Col<MODE_F64>, xy) == 32, "layout");
+static_assert(offsetof(Col<MODE_U16>, xx) == 8 && offsetof(Col<MODE_U16>, xy2) == 24, "layout");
+static_assert(offsetof(Col<MODE_U8>, xy2) == 16, "layout");
+
+// Window sums of one channel along x when the halo reaches only the adjacent
+// lanes (k_x/2 <= R): the left neighbour's suffix sums and the right
+// neighbour's prefix sums arrive by DPP; each output adds its in-lane part
+// (a prefix or a suffix of the lane's columns) and the received sums.
+// Additions only; no partial sum holds a column outside the output's window.
+template <class V, int R, int KW>
+__device__ __forceinline__ void hsum_scalar(const V (&v)[R], V (&out)[R])
+{
+    constexpr int LH = KW / 2;
+    constexpr int RH = KW - 1 - LH;
+    static_assert(LH <= R && RH <= R, "one-hop windows only");
+    V P[R + 1], Q[R + 1];     // P[m]: first m columns; Q[m]: last m columns
+    P[1] = v[0];
+    Q[1] = v[R - 1];
+#pragma unroll
+    for (int m = 2; m <= R; m++) {
+        P[m] = P[m - 1] + v[m - 1];
+        Q[m] = Q[m - 1] + v[R - m];
+    }
+    V Lx[LH + 1], Rx[RH + 1];
+#pragma unroll
+    for (int m = 1; m <= LH; m++) Lx[m] = dpp_move<true>(Q[m]);
+#pragma unroll
+    for (int m = 1; m <= RH; m++) Rx[m] = dpp_move<false>(P[m]);
+#pragma unroll
+    for (int j = 0; j < R; j++) {
+        const int a = j - LH > 0 ? j - LH : 0;
+        const int b = j + RH < R - 1 ? j + RH : R - 1;
+        static_assert(KW + 1 >= R, "in-lane part is a prefix or a suffix");
+        V acc = (a == 0) ? P[b + 1] : Q[R - a];
+        if (j < LH) acc = acc + Lx[LH - j];
+        if (j + RH > R - 1) acc = acc + Rx[j + RH - (R - 1)];
+        out[j] = acc;
+    }
+}
 
 // One row of entering and leaving raw values per lane.
 template <class T, int R> struct Row3 {
@@ -389,7 +474,294 @@ __device__ __forceinline__ void tile3d(const P3D& g, const int tile, char* smem)
     }
 }
 
-template <int M, int R, int KW, int TY, bool VEC>
+// The step for the common shape: k_y == k_x (= KW), unit y step, TY = 2
+// output rows, contiguous rows a multiple of R long (vector loads), planes
+// below 2^30 bytes.  The KW + 1 window rows of a step are unrolled, so which
+// output rows a row feeds is known at compile time: row 0 feeds only output
+// row 0, row KW only output row 1, rows 1..KW-1 both, and their sum is formed
+// once.  Each step's four planes (x and y, entering and leaving) are raw
+// buffers over the whole plane (zero records outside the volume); a row is
+// one offset shared by the four loads, out of range for rows and lanes
+// outside the volume.  Missing values (float input) are screened on the
+// entering values only: until a tile has met one, the planes leaving its
+// window had none either, so the per-element masking runs only from the
+// first missing value on.  The epilogue of a finished plane runs right after
+// the running sum of an output is updated.
+template <int M, int R, int KW>
+__device__ __forceinline__ void tile3d_cube(const P3D& g, const int tile, char* smem)
+{
+    using T = typename Tr<M>::T;
+    constexpr int TY = 2;
+    constexpr int NYR = KW + 1;
+    constexpr int LH = KW / 2;
+    constexpr int NW = Run<T, R>::NW;
+    constexpr bool kFloat = (M == MODE_F64);
+    constexpr uint32_t kFar = 0x40000000u;   // >= every plane's byte size
+    const int lane = threadIdx.x & (kWave - 1);
+
+    // ---- tile geometry (wave-uniform): y fastest, then x, then z ----
+    const int ty = tile % g.tiles_y;
+    const int rest = tile / g.tiles_y;
+    const int tx = rest % g.tiles_x;
+    const int tz = rest / g.tiles_x;
+    const int pz0 = tz * g.TZ;
+    const int pzn = min(g.TZ, g.OD - pz0);
+    const int py0 = ty * TY;
+    const int pyn = min(TY, g.OH - py0);
+    const int q0 = tx * g.Wq;
+    const int qw = min(g.Wq, g.OW - q0);
+    const int D = g.D, H = g.H, W = g.W;
+    const int E = q0 * g.sx + g.ox;
+    const int Eal = (E >= 0) ? (E / R) * R : -((-E + R - 1) / R) * R;
+    const bool fill = g.border == BORDER_FILL;
+    const bool has_flags = g.flags != nullptr;
+
+    // ---- per-lane columns: W is a multiple of R, so a run is wholly inside
+    //      or wholly outside [0, W) ----
+    const int c0 = Eal + lane * R;
+    const uint32_t lane_vo = (c0 >= 0 && c0 < W) ? (uint32_t)c0 * (uint32_t)sizeof(T) : kFar;
+    uint32_t omask = 0, fillb = 0;
+    int qj[R];
+    int ncol[R];
+#pragma unroll
+    for (int j = 0; j < R; j++) {
+        const int qs = c0 + j - g.ox - LH;
+        int q = -1;
+        if (qs >= 0) {
+            q = (g.sx == 1) ? qs : qs / g.sx;
+            if (q * g.sx != qs) q = -1;
+        }
+        omask |= (q >= q0 && q < q0 + qw) ? (1u << j) : 0u;
+        qj[j] = q;
+        const int clo = q * g.sx + g.ox, chi = clo + KW - 1;
+        fillb |= (fill && (clo < 0 || chi >= W)) ? (1u << j) : 0u;
+        ncol[j] = min(chi, W - 1) - max(clo, 0) + 1;
+    }
+
+    const int ys = py0 + g.oy;                       // first window row (unit y step)
+    const int zs = pz0 * g.sz + g.oz;                // first window plane
+    const int nz = (pzn - 1) * g.sz + g.kz;
+    const uint32_t rowbytes = (uint32_t)W * (uint32_t)sizeof(T);
+    const uint32_t planebytes = (uint32_t)H * rowbytes;
+    const char* __restrict__ Xb = (const char*)g.x;
+    const char* __restrict__ Yb = (const char*)g.y;
+    auto prs = [&](const char* A, int z) {
+        const bool ok = (unsigned)z < (unsigned)D;
+        const size_t o = ok ? (size_t)z * (size_t)planebytes : 0;
+        return __builtin_amdgcn_make_buffer_rsrc((void*)(A + o), (short)0,
+                                                 ok ? (int)planebytes : 0, kBufWord3);
+    };
+    // byte offset of window row r (0..NYR-1) for this lane
+    uint32_t voff[NYR];
+#pragma unroll
+    for (int r = 0; r < NYR; r++) {
+        const int row = ys + r;
+        const uint32_t ro = ((unsigned)row < (unsigned)H) ? (uint32_t)row * rowbytes : kFar;
+        voff[r] = lane_vo + ro;
+    }
+
+    constexpr int NDW = S3Slot<M>::NDW;
+    uint32_t* s3w = (uint32_t*)smem;
+    auto slot = [&](int t, int j) { return S3Slot<M>{s3w + (t * R + j) * NDW * kWave}; };
+#pragma unroll
+    for (int t = 0; t < TY; t++)
+#pragma unroll
+        for (int j = 0; j < R; j++) slot(t, j).zero(lane);
+    float hmx = 0.f, hmy = 0.f;
+    bool dirty = false;          // wave-uniform: a missing value has entered this tile
+
+    int next_ready = g.kz - 1;
+    int pz = pz0;
+    for (int li = 0; li < nz; li++) {
+        const int zin = zs + li;
+        const int zout = li >= g.kz ? zin - g.kz : -1;
+        const __amdgpu_buffer_rsrc_t rxi = prs(Xb, zin), ryi = prs(Yb, zin);
+        const __amdgpu_buffer_rsrc_t rxo = prs(Xb, zout), ryo = prs(Yb, zout);
+        Row3<T, R> rw[3];
+        auto issue = [&](int r) __attribute__((always_inline)) {
+            Row3<T, R>& o = rw[r % 3];
+            buf_load_words<NW>(rxi, voff[r], o.xi);
+            buf_load_words<NW>(ryi, voff[r], o.yi);
+            buf_load_words<NW>(rxo, voff[r], o.xo);
+            buf_load_words<NW>(ryo, voff[r], o.yo);
+        };
+        Col<M> V0[R], MID[R];    // MID becomes output row 1's sums after the last row
+        issue(0);
+        issue(1);
+#pragma unroll
+        for (int r = 0; r < NYR; r++) {
+            if (r + 2 < NYR) issue(r + 2);
+            Row3<T, R>& rr = rw[r % 3];
+            T ax[R], ay[R], bx[R], by[R];
+            __builtin_memcpy(ax, rr.xi, sizeof(T) * R);
+            __builtin_memcpy(ay, rr.yi, sizeof(T) * R);
+            __builtin_memcpy(bx, rr.xo, sizeof(T) * R);
+            __builtin_memcpy(by, rr.yo, sizeof(T) * R);
+            int m[R], mo[R];
+#pragma unroll
+            for (int j = 0; j < R; j++) { m[j] = 0; mo[j] = 0; }
+            if constexpr (kFloat) {
+                if (!dirty) {
+                    // entering values: finite and above the threshold?
+                    bool ok = true;
+                    float mxr = 0.f, myr = 0.f;
+#pragma unroll
+                    for (int j = 0; j < R; j++) {
+                        ok = ok & (ax[j] > g.miss_thr) & (ay[j] > g.miss_thr);
+                        mxr = fmaxf(mxr, __builtin_fabsf(ax[j]));
+                        myr = fmaxf(myr, __builtin_fabsf(ay[j]));
+                    }
+                    ok = ok & (mxr < __builtin_inff()) & (myr < __builtin_inff());
+                    hmx = fmaxf(hmx, mxr);
+                    hmy = fmaxf(hmy, myr);
+                    if (__builtin_amdgcn_ballot_w64(!ok)) dirty = true;
+                }
+                if (dirty) {
+#pragma unroll
+                    for (int j = 0; j < R; j++) {
+                        m[j] = (is_missing(ax[j], g.miss_thr) | is_missing(ay[j], g.miss_thr)) ? 1 : 0;
+                        mo[j] = (is_missing(bx[j], g.miss_thr) | is_missing(by[j], g.miss_thr)) ? 1 : 0;
+                        ax[j] = m[j] ? 0.f : ax[j];
+                        ay[j] = m[j] ? 0.f : ay[j];
+                        bx[j] = mo[j] ? 0.f : bx[j];
+                        by[j] = mo[j] ? 0.f : by[j];
+                        hmx = fmaxf(hmx, __builtin_fabsf(ax[j]));
+                        hmy = fmaxf(hmy, __builtin_fabsf(ay[j]));
+                    }
+                }
+            }
+#pragma unroll
+            for (int j = 0; j < R; j++) {
+                const Col<M> d = col_delta<M, T>(ax[j], ay[j], bx[j], by[j], m[j], mo[j]);
+                if (r == 0) {
+                    V0[j] = d;
+                } else if (r == 1) {
+                    MID[j] = d;
+                } else if (r < KW) {
+                    col_add<M>(MID[j], d);
+                } else {
+                    col_add<M>(V0[j], MID[j]);
+                    col_add<M>(MID[j], d);
+                }
+            }
+            __builtin_amdgcn_sched_barrier(0);
+        }
+
+        // ---- x-window sums, running 3-D sums, and (plane finished) the epilogue ----
+        const bool ready = li == next_ready;
+        if (ready) next_ready += g.sz;
+        const int zlo = pz * g.sz + g.oz, zhi = zlo + g.kz - 1;
+        const bool zb = fill && (zlo < 0 || zhi >= D);
+        const double nzp = (double)(min(zhi, D - 1) - max(zlo, 0) + 1);
+        double gx = 0.0, gy = 0.0;
+        if constexpr (kFloat) {
+            if (ready) {
+                float mx = hmx, my = hmy;
+                for (int sft = 1; sft < kWave; sft <<= 1) {
+                    mx = fmaxf(mx, __shfl_xor(mx, sft));
+                    my = fmaxf(my, __shfl_xor(my, sft));
+                }
+                gx = g.cert_g * (double)mx * (double)mx;
+                gy = g.cert_g * (double)my * (double)my;
+            }
+        }
+#pragma unroll
+        for (int t = 0; t < TY; t++) {
+            if (t >= pyn) continue;
+            Col<M>(&VV)[R] = t == 0 ? V0 : MID;
+            // x-window sums channel by channel, added into the running sums
+            auto chan = [&](auto fidx) __attribute__((always_inline)) {
+                constexpr int F = decltype(fidx)::value;
+                using FV = std::remove_reference_t<decltype(col_field<M, F>(VV[0]))>;
+                FV v[R], o[R];
+#pragma unroll
+                for (int j = 0; j < R; j++) v[j] = col_field<M, F>(VV[j]);
+                hsum_scalar<FV, R, KW>(v, o);
+                constexpr int w0 = col_field_word<M, F>();
+#pragma unroll
+                for (int j = 0; j < R; j++) {
+                    uint32_t* b = s3w + (t * R + j) * NDW * kWave + w0 * kWave + lane;
+                    if constexpr (sizeof(FV) == 8) {
+                        uint32_t lo = b[0], hi = b[kWave];
+                        FV cur;
+                        const uint32_t ww[2] = {lo, hi};
+                        __builtin_memcpy(&cur, ww, 8);
+                        cur = cur + o[j];
+                        uint32_t nw[2];
+                        __builtin_memcpy(nw, &cur, 8);
+                        b[0] = nw[0];
+                        b[kWave] = nw[1];
+                    } else {
+                        FV cur;
+                        const uint32_t w = b[0];
+                        __builtin_memcpy(&cur, &w, 4);
+                        cur = cur + o[j];
+                        uint32_t nw;
+                        __builtin_memcpy(&nw, &cur, 4);
+                        b[0] = nw;
+                    }
+                }
+            };
+            chan(std::integral_constant<int, 0>{});
+            chan(std::integral_constant<int, 1>{});
+            chan(std::integral_constant<int, 2>{});
+            chan(std::integral_constant<int, 3>{});
+            chan(std::integral_constant<int, 4>{});
+            if constexpr (col_nfields<M>() == 6) {
+                if (dirty) chan(std::integral_constant<int, 5>{});
+            }
+            if (!ready) continue;
+            const int ylo = (py0 + t) + g.oy, yhi = ylo + KW - 1;
+            const bool rowb = fill && (ylo < 0 || yhi >= H);
+            const double nrow = (double)(min(yhi, H - 1) - max(ylo, 0) + 1);
+            const size_t orow = ((size_t)pz * g.OH + (size_t)(py0 + t)) * (size_t)g.OW;
+#pragma unroll
+            for (int j = 0; j < R; j++) {
+                if (!((omask >> j) & 1u)) continue;
+                const Col<M> A3 = slot(t, j).get(lane);
+                const bool fb = zb || rowb || ((fillb >> j) & 1u);
+                const double dn = nzp * nrow * (double)ncol[j];
+                uint8_t fl = 0;
+                float cv = 0.f;
+                if (fb) {
+                    fl = FL_BORDER;
+                } else if constexpr (kFloat) {
+                    if (A3.miss > 0) {
+                        fl = FL_MISSING;
+                    } else {
+                        const double N = __builtin_fma(dn, A3.xy, -(A3.x * A3.y));
+                        const double Vx = __builtin_fma(dn, A3.xx, -(A3.x * A3.x));
+                        const double Vy = __builtin_fma(dn, A3.yy, -(A3.y * A3.y));
+                        const bool cert = (Vx > gx) && (Vy > gy) && !(g.force & 1);
+                        if (cert) {
+                            cv = clamp_unit(N * rsqrt64(Vx * Vy));
+                        } else {
+                            const int64_t clo = (int64_t)qj[j] * g.sx + g.ox;
+                            fl = twopass_window((const float*)g.x, (const float*)g.y,
+                                                (int64_t)H * W, (int64_t)W, max(zlo, 0),
+                                                min(zhi, D - 1), max(ylo, 0), min(yhi, H - 1),
+                                                max(clo, (int64_t)0),
+                                                min(clo + KW - 1, (int64_t)W - 1), &cv);
+                        }
+                    }
+                } else {
+                    const double sxv = (double)A3.x, syv = (double)A3.y;
+                    const double N = __builtin_fma(0.5 * dn, (double)A3.xy2, -(sxv * syv));
+                    const double Vx = __builtin_fma(dn, (double)A3.xx, -(sxv * sxv));
+                    const double Vy = __builtin_fma(dn, (double)A3.yy, -(syv * syv));
+                    fl = (Vx == 0.0 ? FL_ZVAR_X : 0) | (Vy == 0.0 ? FL_ZVAR_Y : 0);
+                    if (!fl) cv = rn32_certified(N, Vx, Vy, (g.force & 1) != 0);
+                }
+                if (fl) cv = g.invalid;
+                g.c[orow + (uint32_t)qj[j]] = cv;
+                if (has_flags) g.flags[orow + (uint32_t)qj[j]] = fl;
+            }
+        }
+        if (ready) ++pz;
+    }
+}
+
+template <int M, int R, int KW, int TY, bool VEC, bool CUBE>
 __global__ void __launch_bounds__(256)
 __attribute__((amdgpu_waves_per_eu(2, 8))) corr3d_kernel(P3D g)
 {
@@ -398,7 +770,10 @@ __attribute__((amdgpu_waves_per_eu(2, 8))) corr3d_kernel(P3D g)
     const int wpb = blockDim.x / kWave;
     const int tile = xcd_remap(blockIdx.x, gridDim.x) * wpb + wv;
     if (tile >= g.n_tiles) return;
-    tile3d<M, R, KW, TY, VEC>(g, tile, smem + (size_t)wv * tile3d_lds_per_wave<M, TY>(R));
+    if constexpr (CUBE)
+        tile3d_cube<M, R, KW>(g, tile, smem + (size_t)wv * tile3d_lds_per_wave<M, 2>(R));
+    else
+        tile3d<M, R, KW, TY, VEC>(g, tile, smem + (size_t)wv * tile3d_lds_per_wave<M, TY>(R));
 }
 
 }  // namespace swc

@@ -5,31 +5,43 @@
 namespace swc {
 
 template <int KW, int TY>
-static hipError_t go3(const P3D& g, bool vec, int grid, int wpb, hipStream_t s)
+static hipError_t go3(const P3D& g, bool vec, bool cube, int grid, int wpb, hipStream_t s)
 {
     const size_t smem = (size_t)wpb * tile3d_lds_per_wave<MODE_U16, TY>(4);
+    if constexpr (TY == 2) {
+        if (cube && vec) {
+            hipLaunchKernelGGL((corr3d_kernel<MODE_U16, 4, KW, 2, true, true>), dim3(grid),
+                               dim3(wpb * kWave), smem, s, g);
+            return hipGetLastError();
+        }
+    }
     if (vec)
-        hipLaunchKernelGGL((corr3d_kernel<MODE_U16, 4, KW, TY, true>), dim3(grid), dim3(wpb * kWave), smem, s, g);
+        hipLaunchKernelGGL((corr3d_kernel<MODE_U16, 4, KW, TY, true, false>), dim3(grid),
+                           dim3(wpb * kWave), smem, s, g);
     else
-        hipLaunchKernelGGL((corr3d_kernel<MODE_U16, 4, KW, TY, false>), dim3(grid), dim3(wpb * kWave), smem, s, g);
+        hipLaunchKernelGGL((corr3d_kernel<MODE_U16, 4, KW, TY, false, false>), dim3(grid),
+                           dim3(wpb * kWave), smem, s, g);
     return hipGetLastError();
 }
 
 template <int TY>
-static hipError_t pick_kw(const P3D& g, int KW, bool vec, int grid, int wpb, hipStream_t s)
+static hipError_t pick_kw(const P3D& g, int KW, bool vec, bool cube, int grid, int wpb,
+                          hipStream_t s)
 {
     switch (KW) {
-    case 3: return go3<3, TY>(g, vec, grid, wpb, s);
-    case 5: return go3<5, TY>(g, vec, grid, wpb, s);
-    case 7: return go3<7, TY>(g, vec, grid, wpb, s);
-    case 9: return go3<9, TY>(g, vec, grid, wpb, s);
+    case 3: return go3<3, TY>(g, vec, cube, grid, wpb, s);
+    case 5: return go3<5, TY>(g, vec, cube, grid, wpb, s);
+    case 7: return go3<7, TY>(g, vec, cube, grid, wpb, s);
+    case 9: return go3<9, TY>(g, vec, cube, grid, wpb, s);
     default: return hipErrorNotSupported;
     }
 }
 
-hipError_t launch_fast3d_modeu16(const P3D& g, int KW, int TY, bool vec, int grid, int wpb, hipStream_t s)
+hipError_t launch_fast3d_modeu16(const P3D& g, int KW, int TY, bool vec, bool cube, int grid, int wpb,
+                hipStream_t s)
 {
-    return TY == 4 ? pick_kw<4>(g, KW, vec, grid, wpb, s) : pick_kw<2>(g, KW, vec, grid, wpb, s);
+    return TY == 4 ? pick_kw<4>(g, KW, vec, cube, grid, wpb, s)
+                   : pick_kw<2>(g, KW, vec, cube, grid, wpb, s);
 }
 
 }  // namespace swc

@@ -70,3 +70,41 @@ def test_parity_volume_config_full_sampled():
     idx = np.unique(np.concatenate([rng.integers(0, n, 20000), np.arange(3000)]))
     d = compare(x, y, (7, 7, 7), 1, "clip", indices=idx, tag="c4a-full")
     say(f"c4a full (sampled) max|dc| = {d:.3e}")
+
+
+@pytest.mark.parametrize("dtype", ["u8", "u16", "f32"])
+@pytest.mark.parametrize("border", ["fill", "clip", "valid"])
+def test_parity_3d_square_yx_windows(dtype, border):
+    """Square (y, x) windows with unit y step and rows a multiple of 4 long
+    (the specialised step): every x window width, z windows and steps that
+    differ, and agreement with the general step (debug bit 1)."""
+    import paper_1807_06507_amd as swc
+    from gpu_util import gpu_corr
+    for shape, window, step in [((11, 19, 64), (3, 3, 3), 1), ((9, 14, 132), (5, 5, 5), (1, 1, 2)),
+                                ((13, 22, 200), (3, 7, 7), (2, 1, 1)), ((10, 17, 96), (9, 9, 9), 1),
+                                ((8, 9, 40), (1, 5, 5), (3, 1, 3))]:
+        if border == "valid" and any(s < k for s, k in zip(shape, window)):
+            continue
+        x, y = random_pair(shape, dtype, seed=sum(shape) * 3 + sum(window))
+        compare(x, y, window, step, border, tag="3d-square")
+        a, fa = gpu_corr(x, y, window, step, border)
+        swc.set_debug(2)
+        try:
+            b, fb = gpu_corr(x, y, window, step, border)
+        finally:
+            swc.set_debug(0)
+        assert np.array_equal(fa, fb)
+        if dtype != "f32":
+            assert np.array_equal(a.view(np.uint32), b.view(np.uint32))
+
+
+def test_parity_3d_missing_enters_mid_march():
+    """Missing values that first enter a tile's window after many clean
+    planes (and leave it again), on the specialised step."""
+    x, y = random_pair((40, 16, 128), "f32", seed=12, kind="lognormal")
+    x[25, 7, 33] = -1000.0
+    y[31, 2, 90] = np.inf
+    x[38, 15, 127] = np.nan
+    for border in ("clip", "fill"):
+        compare(x, y, (7, 7, 7), 1, border, tag="3d-missing-late", params=(4, 40, 1, 0, 2))
+        compare(x, y, (5, 5, 5), 1, border, tag="3d-missing-late")
