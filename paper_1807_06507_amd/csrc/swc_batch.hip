@@ -183,6 +183,7 @@ swc_status swc_batch_plan_create(int32_t n, const swc_problem* p, const void* co
     auto vec_of = [&](int i) {
         const size_t esz = p[i].dtype == SWC_U8 ? 1 : (p[i].dtype == SWC_U16 ? 2 : 4);
         const size_t va = esz * kBatchR;
+        if (esz == 4) return ((uintptr_t)x[i] % 4 == 0 && (uintptr_t)y[i] % 4 == 0) ? 1 : 0;
         return ((uintptr_t)x[i] % va == 0 && (uintptr_t)y[i] % va == 0 &&
                 p[i].shape[1] % kBatchR == 0) ? 1 : 0;
     };

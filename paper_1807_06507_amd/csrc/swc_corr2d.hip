@@ -326,7 +326,12 @@ hipError_t launch_corr2d(const swc_problem& p, const int64_t* oshape, const Laun
     g.force = force;
     const size_t esz = p.dtype == SWC_U8 ? 1 : (p.dtype == SWC_U16 ? 2 : 4);
     const size_t va = esz * (size_t)L.R;
-    g.vec = ((uintptr_t)x % va == 0 && (uintptr_t)y % va == 0 && (g.W % L.R) == 0) ? 1 : 0;
+    // vector loads of a lane's R-element run: float rows need only 4-byte
+    // alignment (a run crossing the row end reads zeros past it: raw buffer
+    // loads are range-checked per dword); narrower types need whole runs
+    g.vec = (esz == 4) ? ((uintptr_t)x % 4 == 0 && (uintptr_t)y % 4 == 0 ? 1 : 0)
+                       : ((uintptr_t)x % va == 0 && (uintptr_t)y % va == 0 &&
+                          (g.W % L.R) == 0 ? 1 : 0);
 
     // register-resident kernel for compiled window widths (debug bit 2 forces
     // the generic LDS kernel); 32-bit geometry and byte counts (rows are

@@ -492,7 +492,9 @@ __device__ __forceinline__ void tile2d(const P2DF& g, const int tile, char* smem
         colok |= ok ? (1u << j) : 0u;
         cidx[j] = ok ? c : (c < 0 ? 0 : W - 1);
     }
-    // VEC (W a multiple of R): a lane's run is entirely inside or outside [0, W)
+    // VEC: integer rows have W a multiple of R (a run is wholly inside or
+    // outside [0, W)); a float run crossing W reads zeros past it (raw buffer
+    // loads are range-checked per dword)
     // per column: byte offset of its output in the output row (kOffNone when
     // the column is not an output of this tile), clipped column count
     // (packed 8 bits each), FILL-border bit
