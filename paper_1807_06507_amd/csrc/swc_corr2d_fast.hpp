@@ -524,14 +524,21 @@ __device__ __forceinline__ void tile2d(const P2DF& g, const int tile, char* smem
     const uint32_t vfoff = omask ? (uint32_t)c0 : kOffNone;
 
     // ---- per-wave LDS: ring of the last k_h raw rows, zeroed ----
-    uint32_t* ringx = (uint32_t*)smem;                          // [kh][64][NW]
+    // rings of 4+ words per lane are word-major ([kh][NW][64]: 32-bit accesses
+    // of a wave hit 64 consecutive words, no bank conflicts); 1-2 words per
+    // lane stay lane-major ([kh][64][NW], read and written as one access)
+    constexpr bool kWordMajor = NW >= 4;
+    auto ring_at = [&](int slot, int i) __attribute__((always_inline)) {
+        return kWordMajor ? (slot * NW + i) * kWave + lane : (slot * kWave + lane) * NW + i;
+    };
+    uint32_t* ringx = (uint32_t*)smem;
     uint32_t* ringy = ringx + kh * kWave * NW;
     int* ringm = (int*)(ringy + kh * kWave * NW);                // [kh][64] (float input)
     for (int s = 0; s < kh; s++) {
 #pragma unroll
         for (int i = 0; i < NW; i++) {
-            ringx[(s * kWave + lane) * NW + i] = 0u;
-            ringy[(s * kWave + lane) * NW + i] = 0u;
+            ringx[ring_at(s, i)] = 0u;
+            ringy[ring_at(s, i)] = 0u;
         }
         if constexpr (kFloat) ringm[s * kWave + lane] = 0;
     }
@@ -810,10 +817,12 @@ __device__ __forceinline__ void tile2d(const P2DF& g, const int tile, char* smem
                     __builtin_memcpy(wy, vy, sizeof(T) * R);
                 }
                 // ---- leaving row from the ring (zeros for the first k_h rows) ----
-                const int bw = (slot * kWave + lane) * NW;
                 uint32_t ox[NW], oy[NW];
 #pragma unroll
-                for (int i = 0; i < NW; i++) { ox[i] = ringx[bw + i]; oy[i] = ringy[bw + i]; }
+                for (int i = 0; i < NW; i++) {
+                    ox[i] = ringx[ring_at(slot, i)];
+                    oy[i] = ringy[ring_at(slot, i)];
+                }
                 int omiss = 0, nmiss = 0;
                 if constexpr (kFloat) omiss = ringm[slot * kWave + lane];
                 T ax[R], ay[R], bx[R], by[R];
@@ -837,7 +846,10 @@ __device__ __forceinline__ void tile2d(const P2DF& g, const int tile, char* smem
                 }
                 // same lane, same address: the read above returns the old row
 #pragma unroll
-                for (int i = 0; i < NW; i++) { ringx[bw + i] = wx[i]; ringy[bw + i] = wy[i]; }
+                for (int i = 0; i < NW; i++) {
+                    ringx[ring_at(slot, i)] = wx[i];
+                    ringy[ring_at(slot, i)] = wy[i];
+                }
                 slot = (slot + 1 == kh) ? 0 : slot + 1;
                 // ---- step 2: running column sums ----
 #pragma unroll
