@@ -76,15 +76,31 @@ hipError_t launch_corr3d(const swc_problem& p, const int64_t* oshape, const Laun
     // waves per workgroup: halved while the LDS running sums would exceed 64 KB
     int wpb = L.wpb;
     while (wpb > 1 && (int64_t)wpb * tile3d_lds_bytes(mode, L.TY, 4) > 64 * 1024) wpb /= 2;
-    const int grid = (int)((nt + wpb - 1) / wpb);
     const int kw = p.window[2];
     // specialised step: square (y, x) window, unit y step, two rows per wave,
     // vector loads, every plane addressable with 30-bit offsets
     const bool cube = vec && L.TY == 2 && p.window[1] == kw && p.step[1] == 1 &&
                       (int64_t)g.H * g.W * (int64_t)esz < ((int64_t)1 << 30) && !(force & 2);
-    if (mode == MODE_U8) return launch_fast3d_modeu8(g, kw, L.TY, vec, cube, grid, wpb, s);
-    if (mode == MODE_U16) return launch_fast3d_modeu16(g, kw, L.TY, vec, cube, grid, wpb, s);
-    return launch_fast3d_modef64(g, kw, L.TY, vec, cube, grid, wpb, s);
+    // halves: two 32-lane halves of 120 outputs on adjacent row pairs, when
+    // that leaves fewer lanes past the last output column than whole waves
+    int variant = cube ? 1 : 0;
+    if (cube && p.step[2] == 1 && p.border != SWC_BORDER_VALID) {
+        const int64_t lanes_whole = (int64_t)((g.OW + 247) / 248) * 64;
+        const int64_t lanes_half = (int64_t)((g.OW + 119) / 120) * 32;
+        if (lanes_half < lanes_whole) {
+            variant = 2;
+            g.Wq = 120;
+            g.tiles_x = (g.OW + g.Wq - 1) / g.Wq;
+            g.tiles_y = (g.OH + 2 * L.TY - 1) / (2 * L.TY);
+            const int64_t nt2 = (int64_t)g.tiles_x * g.tiles_y * g.tiles_z;
+            if (nt2 >= ((int64_t)1 << 31)) return hipErrorInvalidValue;
+            g.n_tiles = (int)nt2;
+        }
+    }
+    const int grid = (int)(((int64_t)g.n_tiles + wpb - 1) / wpb);
+    if (mode == MODE_U8) return launch_fast3d_modeu8(g, kw, L.TY, vec, variant, grid, wpb, s);
+    if (mode == MODE_U16) return launch_fast3d_modeu16(g, kw, L.TY, vec, variant, grid, wpb, s);
+    return launch_fast3d_modef64(g, kw, L.TY, vec, variant, grid, wpb, s);
 }
 
 }  // namespace swc

@@ -44,13 +44,15 @@ __host__ __device__ inline bool fast3d_supported(int mode, int KW)
     return KW == 3 || KW == 5 || KW == 7 || KW == 9;
 }
 
-// `cube`: use the specialised step (k_y == k_x, unit y step, TY == 2, vector
-// loads, planes below 2^30 bytes); the host checks those conditions.
-hipError_t launch_fast3d_modeu8(const P3D& g, int KW, int TY, bool vec, bool cube, int grid,
+// `cube`: 0 general step; 1 the specialised step (k_y == k_x, unit y step,
+// TY == 2, vector loads, planes below 2^30 bytes); 2 the specialised step in
+// halves (also centred windows, unit x step, Wq = 120, tiles of 4 rows).
+// The host checks those conditions.
+hipError_t launch_fast3d_modeu8(const P3D& g, int KW, int TY, bool vec, int cube, int grid,
                                 int wpb, hipStream_t s);
-hipError_t launch_fast3d_modeu16(const P3D& g, int KW, int TY, bool vec, bool cube, int grid,
+hipError_t launch_fast3d_modeu16(const P3D& g, int KW, int TY, bool vec, int cube, int grid,
                                  int wpb, hipStream_t s);
-hipError_t launch_fast3d_modef64(const P3D& g, int KW, int TY, bool vec, bool cube, int grid,
+hipError_t launch_fast3d_modef64(const P3D& g, int KW, int TY, bool vec, int cube, int grid,
                                  int wpb, hipStream_t s);
 
 // Contribution difference (entering minus leaving) of one element pair, in
@@ -487,7 +489,12 @@ __device__ __forceinline__ void tile3d(const P3D& g, const int tile, char* smem)
 // window had none either, so the per-element masking runs only from the
 // first missing value on.  The epilogue of a finished plane runs right after
 // the running sum of an output is updated.
-template <int M, int R, int KW>
+// HALF: the wave is two 32-lane halves on the same columns (120 outputs per
+// row) and on vertically adjacent row pairs (the wave covers 4 output rows):
+// narrow volumes waste fewer lanes on columns past the last output.  Lanes 0
+// and 31 of each half are its halo; the DPP exchange between the halves only
+// reaches halo lanes, whose outputs are not stored.
+template <int M, int R, int KW, bool HALF>
 __device__ __forceinline__ void tile3d_cube(const P3D& g, const int tile, char* smem)
 {
     using T = typename Tr<M>::T;
@@ -506,7 +513,8 @@ __device__ __forceinline__ void tile3d_cube(const P3D& g, const int tile, char* 
     const int tz = rest / g.tiles_x;
     const int pz0 = tz * g.TZ;
     const int pzn = min(g.TZ, g.OD - pz0);
-    const int py0 = ty * TY;
+    // output rows of this lane: py0, py0 + 1 (per lane in HALF mode)
+    const int py0 = HALF ? ty * (2 * TY) + TY * (lane >> 5) : ty * TY;
     const int pyn = min(TY, g.OH - py0);
     const int q0 = tx * g.Wq;
     const int qw = min(g.Wq, g.OW - q0);
@@ -518,7 +526,7 @@ __device__ __forceinline__ void tile3d_cube(const P3D& g, const int tile, char* 
 
     // ---- per-lane columns: W is a multiple of R, so a run is wholly inside
     //      or wholly outside [0, W) ----
-    const int c0 = Eal + lane * R;
+    const int c0 = Eal + (HALF ? (lane & 31) : lane) * R;
     const uint32_t lane_vo = (c0 >= 0 && c0 < W) ? (uint32_t)c0 * (uint32_t)sizeof(T) : kFar;
     uint32_t omask = 0, fillb = 0;
     int qj[R];
@@ -665,9 +673,11 @@ __device__ __forceinline__ void tile3d_cube(const P3D& g, const int tile, char* 
                 gy = g.cert_g * (double)my * (double)my;
             }
         }
+        // rows of the first (or only) row pair: the most any lane has
+        const int pyn_w = HALF ? min(TY, g.OH - ty * (2 * TY)) : pyn;
 #pragma unroll
         for (int t = 0; t < TY; t++) {
-            if (t >= pyn) continue;
+            if (t >= pyn_w) continue;
             Col<M>(&VV)[R] = t == 0 ? V0 : MID;
             // x-window sums channel by channel, added into the running sums
             auto chan = [&](auto fidx) __attribute__((always_inline)) {
@@ -717,7 +727,7 @@ __device__ __forceinline__ void tile3d_cube(const P3D& g, const int tile, char* 
             const size_t orow = ((size_t)pz * g.OH + (size_t)(py0 + t)) * (size_t)g.OW;
 #pragma unroll
             for (int j = 0; j < R; j++) {
-                if (!((omask >> j) & 1u)) continue;
+                if (!((omask >> j) & 1u) || t >= pyn) continue;
                 const Col<M> A3 = slot(t, j).get(lane);
                 const bool fb = zb || rowb || ((fillb >> j) & 1u);
                 const double dn = nzp * nrow * (double)ncol[j];
@@ -761,7 +771,8 @@ __device__ __forceinline__ void tile3d_cube(const P3D& g, const int tile, char* 
     }
 }
 
-template <int M, int R, int KW, int TY, bool VEC, bool CUBE>
+// CUBE: 0 general step, 1 specialised step, 2 specialised step in halves
+template <int M, int R, int KW, int TY, bool VEC, int CUBE>
 __global__ void __launch_bounds__(256)
 __attribute__((amdgpu_waves_per_eu(2, 8))) corr3d_kernel(P3D g)
 {
@@ -770,8 +781,8 @@ __attribute__((amdgpu_waves_per_eu(2, 8))) corr3d_kernel(P3D g)
     const int wpb = blockDim.x / kWave;
     const int tile = xcd_remap(blockIdx.x, gridDim.x) * wpb + wv;
     if (tile >= g.n_tiles) return;
-    if constexpr (CUBE)
-        tile3d_cube<M, R, KW>(g, tile, smem + (size_t)wv * tile3d_lds_per_wave<M, 2>(R));
+    if constexpr (CUBE != 0)
+        tile3d_cube<M, R, KW, CUBE == 2>(g, tile, smem + (size_t)wv * tile3d_lds_per_wave<M, 2>(R));
     else
         tile3d<M, R, KW, TY, VEC>(g, tile, smem + (size_t)wv * tile3d_lds_per_wave<M, TY>(R));
 }

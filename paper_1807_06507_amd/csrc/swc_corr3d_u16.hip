@@ -5,27 +5,32 @@
 namespace swc {
 
 template <int KW, int TY>
-static hipError_t go3(const P3D& g, bool vec, bool cube, int grid, int wpb, hipStream_t s)
+static hipError_t go3(const P3D& g, bool vec, int cube, int grid, int wpb, hipStream_t s)
 {
     const size_t smem = (size_t)wpb * tile3d_lds_per_wave<MODE_U16, TY>(4);
     if constexpr (TY == 2) {
-        if (cube && vec) {
-            hipLaunchKernelGGL((corr3d_kernel<MODE_U16, 4, KW, 2, true, true>), dim3(grid),
+        if (cube == 2 && vec) {
+            hipLaunchKernelGGL((corr3d_kernel<MODE_U16, 4, KW, 2, true, 2>), dim3(grid),
+                               dim3(wpb * kWave), smem, s, g);
+            return hipGetLastError();
+        }
+        if (cube == 1 && vec) {
+            hipLaunchKernelGGL((corr3d_kernel<MODE_U16, 4, KW, 2, true, 1>), dim3(grid),
                                dim3(wpb * kWave), smem, s, g);
             return hipGetLastError();
         }
     }
     if (vec)
-        hipLaunchKernelGGL((corr3d_kernel<MODE_U16, 4, KW, TY, true, false>), dim3(grid),
+        hipLaunchKernelGGL((corr3d_kernel<MODE_U16, 4, KW, TY, true, 0>), dim3(grid),
                            dim3(wpb * kWave), smem, s, g);
     else
-        hipLaunchKernelGGL((corr3d_kernel<MODE_U16, 4, KW, TY, false, false>), dim3(grid),
+        hipLaunchKernelGGL((corr3d_kernel<MODE_U16, 4, KW, TY, false, 0>), dim3(grid),
                            dim3(wpb * kWave), smem, s, g);
     return hipGetLastError();
 }
 
 template <int TY>
-static hipError_t pick_kw(const P3D& g, int KW, bool vec, bool cube, int grid, int wpb,
+static hipError_t pick_kw(const P3D& g, int KW, bool vec, int cube, int grid, int wpb,
                           hipStream_t s)
 {
     switch (KW) {
@@ -37,7 +42,7 @@ static hipError_t pick_kw(const P3D& g, int KW, bool vec, bool cube, int grid, i
     }
 }
 
-hipError_t launch_fast3d_modeu16(const P3D& g, int KW, int TY, bool vec, bool cube, int grid, int wpb,
+hipError_t launch_fast3d_modeu16(const P3D& g, int KW, int TY, bool vec, int cube, int grid, int wpb,
                 hipStream_t s)
 {
     return TY == 4 ? pick_kw<4>(g, KW, vec, cube, grid, wpb, s)
