@@ -236,7 +236,9 @@ corr1d_kernel(P1D g)
         float a = span_load<T>(bx, i), b = span_load<T>(by, i);
         int m = 0;
         if constexpr (kFloat) {
-            m = (is_missing(a, g.miss_thr) || is_missing(b, g.miss_thr)) ? 1 : 0;
+            // positions outside the series read zero and are never missing
+            const bool inb = i >= dmin && i < nlim;
+            m = (inb && (is_missing(a, g.miss_thr) || is_missing(b, g.miss_thr))) ? 1 : 0;
             if (m) { a = 0.f; b = 0.f; }
         }
         ch_add<M>(part, ch_diff<M>(a, b, 0.f, 0.f, m, 0));
@@ -299,8 +301,13 @@ corr1d_kernel(P1D g)
             if (__builtin_amdgcn_ballot_w64(!clean)) {
 #pragma unroll
                 for (int j = 0; j < R; j++) {
-                    m[j] = (is_missing(r.a[j], g.miss_thr) | is_missing(r.b[j], g.miss_thr)) ? 1 : 0;
-                    mo[j] = (is_missing(r.ao[j], g.miss_thr) | is_missing(r.bo[j], g.miss_thr)) ? 1 : 0;
+                    // positions outside the series read zero and are never missing
+                    const bool in_i = d0 + j >= dmin && d0 + j < nlim;
+                    const bool in_o = d0 - k + j >= dmin && d0 - k + j < nlim;
+                    m[j] = (in_i && (is_missing(r.a[j], g.miss_thr) |
+                                     is_missing(r.b[j], g.miss_thr))) ? 1 : 0;
+                    mo[j] = (in_o && (is_missing(r.ao[j], g.miss_thr) |
+                                      is_missing(r.bo[j], g.miss_thr))) ? 1 : 0;
                     r.a[j] = m[j] ? 0.f : r.a[j];
                     r.b[j] = m[j] ? 0.f : r.b[j];
                     r.ao[j] = mo[j] ? 0.f : r.ao[j];

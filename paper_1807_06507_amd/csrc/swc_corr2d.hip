@@ -49,7 +49,9 @@ template <class T, int R>
 __device__ __forceinline__ void load_run(const T* __restrict__ row, int64_t c0, int64_t W,
                                          bool vec, T (&v)[R])
 {
-    if (vec && c0 >= 0 && c0 + R <= W) {
+    // whole run inside the row and aligned for one vector load (float rows
+    // of any width may reach here with `vec` set, unaligned)
+    if (vec && c0 >= 0 && c0 + R <= W && (uintptr_t)(row + c0) % (sizeof(T) * R) == 0) {
         const T* p = (const T*)__builtin_assume_aligned(row + c0, sizeof(T) * R);
         __builtin_memcpy(v, p, sizeof(T) * R);
     } else {
@@ -115,7 +117,9 @@ __global__ void __launch_bounds__(256) corr2d_kernel(P2D g)
             }
 #pragma unroll
             for (int j = 0; j < R; j++) {
-                Elem<M> e = make_elem<M>(ax[j], ay[j], g.miss_thr);
+                const int64_t cj = col0 + j;
+                const bool inb = i >= 0 && i < H && cj >= 0 && cj < W;
+                Elem<M> e = make_elem<M>(ax[j], ay[j], g.miss_thr, inb);
                 acc_add<M>(V[j], e);
                 if constexpr (!Tr<M>::kInt) {
                     if (!e.miss) {
@@ -138,7 +142,9 @@ __global__ void __launch_bounds__(256) corr2d_kernel(P2D g)
             }
 #pragma unroll
             for (int j = 0; j < R; j++) {
-                Elem<M> e = make_elem<M>(ax[j], ay[j], g.miss_thr);
+                const int64_t cj = col0 + j;
+                const bool inb = io >= 0 && io < H && cj >= 0 && cj < W;
+                Elem<M> e = make_elem<M>(ax[j], ay[j], g.miss_thr, inb);
                 acc_sub<M>(V[j], e);
             }
         }

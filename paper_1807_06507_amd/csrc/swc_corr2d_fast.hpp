@@ -824,16 +824,21 @@ __device__ __forceinline__ void tile2d(const P2DF& g, const int tile, char* smem
                     oy[i] = ringy[ring_at(slot, i)];
                 }
                 int omiss = 0, nmiss = 0;
-                if constexpr (kFloat) omiss = ringm[slot * kWave + lane];
                 T ax[R], ay[R], bx[R], by[R];
                 __builtin_memcpy(ax, wx, sizeof(T) * R);
                 __builtin_memcpy(ay, wy, sizeof(T) * R);
                 __builtin_memcpy(bx, ox, sizeof(T) * R);
                 __builtin_memcpy(by, oy, sizeof(T) * R);
                 if constexpr (kFloat) {
+                    omiss = ringm[slot * kWave + lane];
+                    // positions outside the array read zero and are never
+                    // missing, whatever the threshold
+                    const bool row_in = (unsigned)row < (unsigned)H;
 #pragma unroll
                     for (int j = 0; j < R; j++) {
-                        const bool m = is_missing(ax[j], g.miss_thr) || is_missing(ay[j], g.miss_thr);
+                        const bool inb = row_in && ((colok >> j) & 1u);
+                        const bool m = inb && (is_missing(ax[j], g.miss_thr) ||
+                                               is_missing(ay[j], g.miss_thr));
                         ax[j] = m ? 0.f : ax[j];
                         ay[j] = m ? 0.f : ay[j];
                         nmiss |= m ? (1 << j) : 0;

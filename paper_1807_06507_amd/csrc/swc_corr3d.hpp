@@ -360,10 +360,17 @@ __device__ __forceinline__ void tile3d(const P3D& g, const int tile, char* smem)
                 }
                 const bool clean = (lo > g.miss_thr) & (hi < __builtin_inff()) & !nan;
                 if (__builtin_amdgcn_ballot_w64(!clean)) {
+                    // positions outside the volume read zero and are never missing
+                    const bool row_in = (unsigned)(ys + r) < (unsigned)H;
+                    const bool in_i = row_in && (unsigned)zin < (unsigned)D;
+                    const bool in_o = row_in && (unsigned)zout < (unsigned)D;
 #pragma unroll
                     for (int j = 0; j < R; j++) {
-                        m[j] = (is_missing(ax[j], g.miss_thr) | is_missing(ay[j], g.miss_thr)) ? 1 : 0;
-                        mo[j] = (is_missing(bx[j], g.miss_thr) | is_missing(by[j], g.miss_thr)) ? 1 : 0;
+                        const bool col_in = (colok >> j) & 1u;
+                        m[j] = (in_i && col_in &&
+                                (is_missing(ax[j], g.miss_thr) | is_missing(ay[j], g.miss_thr))) ? 1 : 0;
+                        mo[j] = (in_o && col_in &&
+                                 (is_missing(bx[j], g.miss_thr) | is_missing(by[j], g.miss_thr))) ? 1 : 0;
                         ax[j] = m[j] ? 0.f : ax[j];
                         ay[j] = m[j] ? 0.f : ay[j];
                         bx[j] = mo[j] ? 0.f : bx[j];
@@ -620,15 +627,24 @@ __device__ __forceinline__ void tile3d_cube(const P3D& g, const int tile, char* 
                         myr = fmaxf(myr, __builtin_fabsf(ay[j]));
                     }
                     ok = ok & (mxr < __builtin_inff()) & (myr < __builtin_inff());
-                    hmx = fmaxf(hmx, mxr);
-                    hmy = fmaxf(hmy, myr);
-                    if (__builtin_amdgcn_ballot_w64(!ok)) dirty = true;
+                    if (__builtin_amdgcn_ballot_w64(!ok)) {
+                        dirty = true;             // the per-element path below bounds |x|
+                    } else {
+                        hmx = fmaxf(hmx, mxr);
+                        hmy = fmaxf(hmy, myr);
+                    }
                 }
                 if (dirty) {
+                    // positions outside the volume read zero and are never missing
+                    const bool row_in = (unsigned)(ys + r) < (unsigned)H && c0 >= 0 && c0 < W;
+                    const bool in_i = row_in && (unsigned)zin < (unsigned)D;
+                    const bool in_o = row_in && (unsigned)zout < (unsigned)D;
 #pragma unroll
                     for (int j = 0; j < R; j++) {
-                        m[j] = (is_missing(ax[j], g.miss_thr) | is_missing(ay[j], g.miss_thr)) ? 1 : 0;
-                        mo[j] = (is_missing(bx[j], g.miss_thr) | is_missing(by[j], g.miss_thr)) ? 1 : 0;
+                        m[j] = (in_i && (is_missing(ax[j], g.miss_thr) |
+                                         is_missing(ay[j], g.miss_thr))) ? 1 : 0;
+                        mo[j] = (in_o && (is_missing(bx[j], g.miss_thr) |
+                                          is_missing(by[j], g.miss_thr))) ? 1 : 0;
                         ax[j] = m[j] ? 0.f : ax[j];
                         ay[j] = m[j] ? 0.f : ay[j];
                         bx[j] = mo[j] ? 0.f : bx[j];

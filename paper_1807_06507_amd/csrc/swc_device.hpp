@@ -130,8 +130,11 @@ __device__ __forceinline__ bool is_missing(float v, float thr)
 
 // Element contribution from raw values.  `thr` is the missing threshold as
 // float (x <= missing_le <=> x <= thr for float x, see the host side).
+// `inb`: the position lies inside the array (positions outside read as zero
+// and are never missing, whatever the threshold).
 template <int M>
-__device__ __forceinline__ Elem<M> make_elem(typename Tr<M>::T vx, typename Tr<M>::T vy, float thr)
+__device__ __forceinline__ Elem<M> make_elem(typename Tr<M>::T vx, typename Tr<M>::T vy, float thr,
+                                             bool inb = true)
 {
     Elem<M> e;
     if constexpr (M == MODE_U8) {
@@ -146,7 +149,7 @@ __device__ __forceinline__ Elem<M> make_elem(typename Tr<M>::T vx, typename Tr<M
         e.xx = da * da; e.xy = da * db; e.yy = db * db;   // exact (< 2^32)
         e.miss = 0;
     } else {
-        bool m = is_missing(vx, thr) || is_missing(vy, thr);
+        bool m = inb && (is_missing(vx, thr) || is_missing(vy, thr));
         float a = m ? 0.f : vx;
         float b = m ? 0.f : vy;
         e.miss = m ? 1 : 0;

@@ -44,18 +44,20 @@ def gpu_corr(x, y, window, step=1, border="fill", accum="default", params=None,
 
 
 def compare(x, y, window, step=1, border="fill", accum="default", params=None, tag="",
-            indices=None, tol=None, scheme=None):
+            indices=None, tol=None, scheme=None, missing_le=-999.0):
     """Run both sides, assert parity, return max |dc| over valid outputs.
     ``scheme`` selects one of the unfused baseline schemes instead of the
     fused kernels."""
     say(f"[parity] {tag} shape={x.shape} dtype={x.dtype} window={window} step={step} "
         f"border={border} accum={accum} params={params} scheme={scheme}")
-    c, fl = gpu_corr(x, y, window, step, border, accum, params, scheme=scheme)
+    c, fl = gpu_corr(x, y, window, step, border, accum, params, scheme=scheme,
+                     missing_le=missing_le)
     if indices is None:
-        o32, o64, ofl = oracle.corr(x, y, window, step, border)
+        o32, o64, ofl = oracle.corr(x, y, window, step, border, missing_le=missing_le)
         c_cmp, fl_cmp = c, fl
     else:
-        o32, o64, ofl = oracle.corr(x, y, window, step, border, indices=indices)
+        o32, o64, ofl = oracle.corr(x, y, window, step, border, missing_le=missing_le,
+                                    indices=indices)
         c_cmp, fl_cmp = c.ravel()[indices], fl.ravel()[indices]
     assert c_cmp.shape == o32.shape, (c_cmp.shape, o32.shape)
     if accum != "default":
