@@ -44,7 +44,7 @@ WORKLOADS = {
     "c2": dict(desc="4096x4096 float32 offset pair (precision case k=7, s=1), CLIP",
                shape=(4096, 4096), dtype="f32", window=(7, 7), step=(1, 1), border="clip"),
     "c3": dict(desc="64 float32 cloud pairs, 256..4096 x 256..3072, windows {5,7,9,15}, step 1, "
-                    "CLIP, one persistent launch", batched=True, dtype="f32"),
+                    "CLIP, persistent launches", batched=True, dtype="f32"),
     "c4a": dict(desc="512x512x256 float32 smoothed-normal volume pair, window 7x7x7, step 1, CLIP",
                 shape=(256, 512, 512), dtype="f32", window=(7, 7, 7), step=(1, 1, 1),
                 border="clip"),
@@ -246,7 +246,7 @@ def host_pipeline(torch, swc, x, y, w, reps=5):
 
 
 def run_batched(args, torch, swc, dev):
-    """The batched workload: one persistent launch over all 64 pairs, against
+    """The batched workload: persistent launches over all 64 pairs, against
     64 per-image launches (eager and captured in one graph)."""
     from workloads import batched_pairs
     w = WORKLOADS["c3"]

@@ -247,7 +247,7 @@ swc_status swc_tune_set(const swc_problem *p, const swc_launch_params *lp);
 /* Parameters swc_corr would use for `p` (tuned entry or built-in default). */
 swc_status swc_tune_get(const swc_problem *p, swc_launch_params *lp);
 
-/* ---- batches of independent pairs (one persistent launch) -------------- */
+/* ---- batches of independent pairs (persistent launches) ---------------- */
 
 typedef struct swc_batch_plan swc_batch_plan;
 
@@ -265,8 +265,11 @@ swc_status swc_batch_plan_create(int32_t n, const swc_problem *p, const void *co
                                  uint8_t *const *flags, const swc_launch_params *lp,
                                  swc_batch_plan **out);
 
-/* One persistent launch computing every pair of the plan on `stream`.
- * Asynchronous, allocates nothing, safe to capture into a hipGraph. */
+/* Compute every pair of the plan on `stream`: persistent launches, one per
+ * group of pairs whose LDS rings allow the same number of resident
+ * wavefronts per CU (at most four), plus one ordinary launch per pair without
+ * a compiled window width.  Asynchronous, allocates nothing, safe to capture
+ * into a hipGraph. */
 swc_status swc_batch_launch(const swc_batch_plan *plan, void *stream);
 
 /* Number of work items (tiles) in the plan, for reporting. */

@@ -1,16 +1,20 @@
-// Batched correlation of many independent 2-D pairs in one persistent launch.
+// Batched correlation of many independent 2-D pairs in persistent launches.
 //
-// A plan turns n problems (different shapes, windows, steps, borders) into a
-// single list of tiles: the tiles of pair i occupy [tile0_i, tile0_i + n_i).
+// A plan turns n problems (different shapes, windows, steps, borders) into
+// lists of tiles: in a list, the tiles of pair i occupy [tile0_i, tile0_i + n_i).
 // The device holds one descriptor per pair (the same tile geometry the
-// single-pair register kernel uses).  One launch of a fixed grid of
-// wavefronts walks the list: wave w takes items w, w + W, w + 2W, ...,
+// single-pair register kernel uses).  One launch of a fixed, fully resident
+// grid of wavefronts walks a list: wave w takes items w, w + W, w + 2W, ...,
 // finds the pair by binary search over tile0 and runs the tile with the
-// kernel variant of that pair's window width.  Pairs are ordered by
-// (window, alignment) so that waves running at the same time mostly share
-// one code path.  Pairs without a compiled variant are computed by their own
-// launches, issued by the same swc_batch_launch call (still capture-safe:
-// no allocation, copy or synchronisation).
+// kernel variant of that pair's window width.  A launch reserves, for every
+// wave, the LDS ring of its widest window, which caps the resident waves per
+// CU; pairs are therefore grouped by that cap (at most four groups, each one
+// persistent launch), so narrow windows are not held to the occupancy of the
+// widest.  Within a list pairs are ordered by (window, alignment) so that
+// waves running at the same time mostly share one code path.  Pairs without a
+// compiled variant are computed by their own launches, issued by the same
+// swc_batch_launch call (still capture-safe: no allocation, copy or
+// synchronisation).
 #include <stdlib.h>
 #include <string.h>
 
@@ -80,14 +84,21 @@ static bool batch_kw_ok(int kw) { return kw == 3 || kw == 5 || kw == 7 || kw == 
 
 using namespace swc;
 
-struct swc_batch_plan {
-    int mode;
+// One persistent launch: a list of pairs with a common LDS stride.
+struct BatchGroup {
+    const BatchItem* d_items;    // into the plan's allocation
     int n_items;
     int64_t total_tiles;
     int lds_stride;
     int wpb;
     int64_t nwaves;
-    BatchItem* d_items;          // device, owned
+};
+
+struct swc_batch_plan {
+    int mode;
+    std::vector<BatchGroup> groups;
+    int64_t total_tiles;
+    BatchItem* d_items;          // device, owned (all groups' lists, concatenated)
     // pairs computed by their own launches
     std::vector<swc_problem> rest_p;
     std::vector<std::array<const void*, 2>> rest_xy;
@@ -103,6 +114,27 @@ namespace swc {
 LaunchCfg batch_pair_cfg(const swc_problem& p);
 bool tune_lookup(int dtype, int ndim, int accum, int kb, swc_launch_params* out);
 }
+
+namespace {
+
+// Resident workgroups per CU of the batch kernel for a launch shape.
+int batch_blocks_per_cu(int mode, int wpb, size_t smem)
+{
+    int n = 0;
+    hipError_t e;
+    if (mode == MODE_U8)
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, corr2d_batch_kernel<MODE_U8>,
+                                                         wpb * kWave, smem);
+    else if (mode == MODE_U16)
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, corr2d_batch_kernel<MODE_U16>,
+                                                         wpb * kWave, smem);
+    else
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, corr2d_batch_kernel<MODE_F64>,
+                                                         wpb * kWave, smem);
+    return (e == hipSuccess && n > 0) ? n : 1;
+}
+
+}  // namespace
 
 extern "C" {
 
@@ -148,12 +180,17 @@ swc_status swc_batch_plan_create(int32_t n, const swc_problem* p, const void* co
                p[i].shape[1] < (1ll << 28) &&   // rows are raw buffers (< 2^31 bytes)
                fast2d_lds_per_wave(mode, kBatchR, p[i].window[0]) <= 64 * 1024;
     };
-    // waves per workgroup: the largest (at most the requested) whose LDS rings fit in 64 KB
-    int lds_need = 0;
+    // per pair: LDS ring bytes per wave, and the resident waves per CU that
+    // ring allows; pairs with the same cap share one persistent launch
+    int lds_cu = 160 * 1024;
+    hipDeviceGetAttribute(&lds_cu, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, dev);
+    auto lds_of = [&](int i) {
+        return (fast2d_lds_per_wave(mode, kBatchR, p[i].window[0]) + 15) & ~15;
+    };
+    auto cap_of = [&](int i) { return std::min(8, std::max(1, lds_cu / lds_of(i))); };
     int64_t tile_rows_total = 0;   // sum over pairs of output rows x tile columns
     for (int i = 0; i < n; i++) {
         if (!eligible(i)) continue;
-        lds_need = std::max(lds_need, fast2d_lds_per_wave(mode, kBatchR, p[i].window[0]));
         int64_t osh[3];
         swc_output_shape(&p[i], osh);
         const bool contig = p[i].step[1] == 1 && p[i].border != SWC_BORDER_VALID;
@@ -161,25 +198,22 @@ swc_status swc_batch_plan_create(int32_t n, const swc_problem* p, const void* co
                               : (kWave * kBatchR - (kBatchR - 1) - p[i].window[1]) / p[i].step[1] + 1;
         tile_rows_total += osh[0] * ((osh[1] + wq - 1) / wq);
     }
-    lds_need = (lds_need + 15) & ~15;
-    if (wpb == 0) wpb = 4;
-    while (wpb > 1 && (int64_t)wpb * lds_need > 64 * 1024) wpb /= 2;
-    // persistent grid: a few waves per SIMD
+    // persistent grid: a few waves per SIMD at most
     const int64_t target = (int64_t)cus * 4 * (minw > 0 ? minw : 2);
     // tile height: about four tiles per persistent wave, 16..128 rows
     if (TH == 0)
         TH = (int)std::min<int64_t>(128, std::max<int64_t>(16, tile_rows_total / (4 * target)));
+    const int wpb_req = wpb == 0 ? 4 : wpb;
 
     swc_batch_plan* plan = new swc_batch_plan();
     plan->mode = mode;
     plan->device = dev;
-    plan->wpb = wpb;
     std::vector<BatchItem> items;
     std::vector<int> order(n);
     for (int i = 0; i < n; i++) order[i] = i;
-    // widest windows first (their tiles cost the most, so the tail of the
-    // persistent loop is made of cheap tiles), then by alignment so
-    // concurrent waves share code
+    // groups by occupancy cap (lowest first); inside a group widest windows
+    // first (their tiles cost the most, so the tail of the persistent loop is
+    // made of cheap tiles), then by alignment so concurrent waves share code
     auto vec_of = [&](int i) {
         const size_t esz = p[i].dtype == SWC_U8 ? 1 : (p[i].dtype == SWC_U16 ? 2 : 4);
         const size_t va = esz * kBatchR;
@@ -187,23 +221,39 @@ swc_status swc_batch_plan_create(int32_t n, const swc_problem* p, const void* co
         return ((uintptr_t)x[i] % va == 0 && (uintptr_t)y[i] % va == 0 &&
                 p[i].shape[1] % kBatchR == 0) ? 1 : 0;
     };
+    std::vector<int> cap(n, 8);
+    for (int i = 0; i < n; i++)
+        if (eligible(i)) cap[i] = cap_of(i);
     std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+        if (cap[a] != cap[b]) return cap[a] < cap[b];
         if (p[a].window[1] != p[b].window[1]) return p[a].window[1] > p[b].window[1];
         return vec_of(a) > vec_of(b);
     });
+    // at most four groups: caps beyond the fourth distinct value join the last
+    std::vector<int> group_of(n, 0);
+    {
+        int g = -1, last_cap = -1;
+        for (int oi = 0; oi < n; oi++) {
+            const int i = order[oi];
+            if (!eligible(i)) continue;
+            if (cap[i] != last_cap && g < 3) {
+                ++g;
+                last_cap = cap[i];
+            }
+            group_of[i] = g;
+        }
+    }
+    std::vector<int> gstart;       // first item index of each group
+    std::vector<int64_t> gtiles;
+    std::vector<int> glds;
     int64_t tile0 = 0;
-    int lds_max = 0;
+    int cur_group = -1;
     for (int oi = 0; oi < n; oi++) {
         const int i = order[oi];
         const swc_problem& q = p[i];
         int64_t osh[3];
         swc_output_shape(&q, osh);
         const bool fast = eligible(i);
-        LaunchCfg L;
-        L.R = kBatchR;
-        L.TH = TH;
-        L.wpb = wpb;
-        L.minw = minw;
         if (!fast) {
             plan->rest_p.push_back(q);
             plan->rest_xy.push_back({x[i], y[i]});
@@ -212,6 +262,13 @@ swc_status swc_batch_plan_create(int32_t n, const swc_problem* p, const void* co
             plan->rest_osh.push_back({osh[0], osh[1], osh[2]});
             plan->rest_cfg.push_back(batch_pair_cfg(q));
             continue;
+        }
+        if (group_of[i] != cur_group) {
+            cur_group = group_of[i];
+            gstart.push_back((int)items.size());
+            gtiles.push_back(0);
+            glds.push_back(0);
+            tile0 = 0;
         }
         BatchItem b;
         memset(&b, 0, sizeof b);
@@ -251,17 +308,14 @@ swc_status swc_batch_plan_create(int32_t n, const swc_problem* p, const void* co
         b.tile0 = tile0;
         b.kw = q.window[1];
         b.vec = vec_of(i);
-        b.lds = fast2d_lds_per_wave(mode, kBatchR, q.window[0]);
-        lds_max = std::max(lds_max, b.lds);
+        b.lds = lds_of(i);
+        glds.back() = std::max(glds.back(), b.lds);
         tile0 += g.n_tiles;
+        gtiles.back() = tile0;
         items.push_back(b);
     }
-    plan->n_items = (int)items.size();
-    plan->total_tiles = tile0;
-    plan->lds_stride = (lds_max + 15) & ~15;
-    // never more waves than the work
-    plan->nwaves = std::max<int64_t>(1, std::min<int64_t>(target, tile0));
     plan->d_items = nullptr;
+    plan->total_tiles = 0;
     if (!items.empty()) {
         if (hipMalloc((void**)&plan->d_items, items.size() * sizeof(BatchItem)) != hipSuccess) {
             delete plan;
@@ -274,6 +328,23 @@ swc_status swc_batch_plan_create(int32_t n, const swc_problem* p, const void* co
             return SWC_ERR_DEVICE;
         }
     }
+    for (size_t gi = 0; gi < gstart.size(); gi++) {
+        BatchGroup G;
+        G.d_items = plan->d_items + gstart[gi];
+        G.n_items = (gi + 1 < gstart.size() ? gstart[gi + 1] : (int)items.size()) - gstart[gi];
+        G.total_tiles = gtiles[gi];
+        G.lds_stride = glds[gi];
+        // waves per workgroup: the largest (at most the requested) whose rings fit in 64 KB
+        int w = wpb_req;
+        while (w > 1 && (int64_t)w * G.lds_stride > 64 * 1024) w /= 2;
+        G.wpb = w;
+        // a fully resident grid: never more waves than fit at once, nor than the work
+        const int64_t resident =
+            (int64_t)cus * batch_blocks_per_cu(mode, w, (size_t)G.lds_stride * w) * w;
+        G.nwaves = std::max<int64_t>(1, std::min<int64_t>(std::min(target, resident), G.total_tiles));
+        plan->groups.push_back(G);
+        plan->total_tiles += G.total_tiles;
+    }
     *out = plan;
     return SWC_OK;
 }
@@ -282,25 +353,22 @@ swc_status swc_batch_launch(const swc_batch_plan* plan, void* stream)
 {
     if (!plan) return SWC_ERR_NULL;
     hipStream_t s = (hipStream_t)stream;
-    if (plan->n_items > 0) {
-        const int grid = (int)((plan->nwaves + plan->wpb - 1) / plan->wpb);
-        const size_t smem = (size_t)plan->lds_stride * plan->wpb;
-        const dim3 blk(plan->wpb * kWave);
+    for (const BatchGroup& G : plan->groups) {
+        const int grid = (int)((G.nwaves + G.wpb - 1) / G.wpb);
+        const size_t smem = (size_t)G.lds_stride * G.wpb;
+        const dim3 blk(G.wpb * kWave);
         switch (plan->mode) {
         case MODE_U8:
             hipLaunchKernelGGL((corr2d_batch_kernel<MODE_U8>), dim3(grid), blk, smem, s,
-                               plan->d_items, plan->n_items, plan->total_tiles, plan->nwaves,
-                               plan->lds_stride);
+                               G.d_items, G.n_items, G.total_tiles, G.nwaves, G.lds_stride);
             break;
         case MODE_U16:
             hipLaunchKernelGGL((corr2d_batch_kernel<MODE_U16>), dim3(grid), blk, smem, s,
-                               plan->d_items, plan->n_items, plan->total_tiles, plan->nwaves,
-                               plan->lds_stride);
+                               G.d_items, G.n_items, G.total_tiles, G.nwaves, G.lds_stride);
             break;
         default:
             hipLaunchKernelGGL((corr2d_batch_kernel<MODE_F64>), dim3(grid), blk, smem, s,
-                               plan->d_items, plan->n_items, plan->total_tiles, plan->nwaves,
-                               plan->lds_stride);
+                               G.d_items, G.n_items, G.total_tiles, G.nwaves, G.lds_stride);
             break;
         }
         if (hipGetLastError() != hipSuccess) return SWC_ERR_LAUNCH;
