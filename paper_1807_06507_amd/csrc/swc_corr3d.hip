@@ -73,9 +73,6 @@ hipError_t launch_corr3d(const swc_problem& p, const int64_t* oshape, const Laun
     const size_t esz = p.dtype == SWC_U8 ? 1 : (p.dtype == SWC_U16 ? 2 : 4);
     const bool vec = ((uintptr_t)x % (esz * 4) == 0) && ((uintptr_t)y % (esz * 4) == 0) &&
                      (g.W % 4 == 0);
-    // waves per workgroup: halved while the LDS running sums would exceed 64 KB
-    int wpb = L.wpb;
-    while (wpb > 1 && (int64_t)wpb * tile3d_lds_bytes(mode, L.TY, 4) > 64 * 1024) wpb /= 2;
     const int kw = p.window[2];
     // specialised step: square (y, x) window, unit y step, two rows per wave,
     // vector loads, every plane addressable with 30-bit offsets
@@ -97,6 +94,10 @@ hipError_t launch_corr3d(const swc_problem& p, const int64_t* oshape, const Laun
             g.n_tiles = (int)nt2;
         }
     }
+    // waves per workgroup: halved while the LDS running sums would exceed 64 KB
+    const int lds_wave = cube ? cube_lds_bytes(mode, 4) : tile3d_lds_bytes(mode, L.TY, 4);
+    int wpb = L.wpb;
+    while (wpb > 1 && (int64_t)wpb * lds_wave > 64 * 1024) wpb /= 2;
     const int grid = (int)(((int64_t)g.n_tiles + wpb - 1) / wpb);
     if (mode == MODE_U8) return launch_fast3d_modeu8(g, kw, L.TY, vec, variant, grid, wpb, s);
     if (mode == MODE_U16) return launch_fast3d_modeu16(g, kw, L.TY, vec, variant, grid, wpb, s);

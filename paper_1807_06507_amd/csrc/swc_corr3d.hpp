@@ -81,6 +81,22 @@ template <int M, int TY> __host__ __device__ constexpr int tile3d_lds_per_wave(i
 {
     return TY * R * (int)sizeof(Col<M>) * kWave;
 }
+// The specialised step keeps the missing counts in registers: float slots
+// hold the five FP64 sums only (10 words), so 8 waves' sums fit one CU.
+template <int M> __host__ __device__ constexpr int cube_slot_words()
+{
+    return M == MODE_F64 ? 10 : (int)(sizeof(Col<M>) / 4);
+}
+template <int M> __host__ __device__ constexpr int cube_lds_per_wave(int R)
+{
+    return 2 * R * cube_slot_words<M>() * 4 * kWave;
+}
+__host__ __device__ inline int cube_lds_bytes(int mode, int R)
+{
+    return mode == MODE_U8 ? cube_lds_per_wave<MODE_U8>(R)
+                           : (mode == MODE_U16 ? cube_lds_per_wave<MODE_U16>(R)
+                                               : cube_lds_per_wave<MODE_F64>(R));
+}
 __host__ __device__ inline int tile3d_lds_bytes(int mode, int TY, int R)
 {
     const int cb = mode == MODE_U8 ? (int)sizeof(Col<MODE_U8>)
@@ -575,13 +591,21 @@ __device__ __forceinline__ void tile3d_cube(const P3D& g, const int tile, char* 
         voff[r] = lane_vo + ro;
     }
 
-    constexpr int NDW = S3Slot<M>::NDW;
+    // running 3-D sums: LDS slot (t, j) holds the FP64 (or integer) sums,
+    // lane-strided; float input keeps the missing counts in registers
+    constexpr int NDW = cube_slot_words<M>();
     uint32_t* s3w = (uint32_t*)smem;
-    auto slot = [&](int t, int j) { return S3Slot<M>{s3w + (t * R + j) * NDW * kWave}; };
 #pragma unroll
     for (int t = 0; t < TY; t++)
 #pragma unroll
-        for (int j = 0; j < R; j++) slot(t, j).zero(lane);
+        for (int j = 0; j < R; j++)
+#pragma unroll
+            for (int i = 0; i < NDW; i++) s3w[((t * R + j) * NDW + i) * kWave + lane] = 0u;
+    int s3miss[TY][R];
+#pragma unroll
+    for (int t = 0; t < TY; t++)
+#pragma unroll
+        for (int j = 0; j < R; j++) s3miss[t][j] = 0;
     float hmx = 0.f, hmy = 0.f;
     bool dirty = false;          // wave-uniform: a missing value has entered this tile
 
@@ -703,6 +727,11 @@ __device__ __forceinline__ void tile3d_cube(const P3D& g, const int tile, char* 
 #pragma unroll
                 for (int j = 0; j < R; j++) v[j] = col_field<M, F>(VV[j]);
                 hsum_scalar<FV, R, KW>(v, o);
+                if constexpr (M == MODE_F64 && F == 5) {
+#pragma unroll
+                    for (int j = 0; j < R; j++) s3miss[t][j] += o[j];
+                    return;
+                }
                 constexpr int w0 = col_field_word<M, F>();
 #pragma unroll
                 for (int j = 0; j < R; j++) {
@@ -744,7 +773,14 @@ __device__ __forceinline__ void tile3d_cube(const P3D& g, const int tile, char* 
 #pragma unroll
             for (int j = 0; j < R; j++) {
                 if (!((omask >> j) & 1u) || t >= pyn) continue;
-                const Col<M> A3 = slot(t, j).get(lane);
+                Col<M> A3;
+                {
+                    uint32_t w[NDW];
+#pragma unroll
+                    for (int i = 0; i < NDW; i++) w[i] = s3w[((t * R + j) * NDW + i) * kWave + lane];
+                    __builtin_memcpy(&A3, w, NDW * 4);
+                    if constexpr (M == MODE_F64) A3.miss = s3miss[t][j];
+                }
                 const bool fb = zb || rowb || ((fillb >> j) & 1u);
                 const double dn = nzp * nrow * (double)ncol[j];
                 uint8_t fl = 0;
@@ -798,7 +834,7 @@ __attribute__((amdgpu_waves_per_eu(2, 8))) corr3d_kernel(P3D g)
     const int tile = xcd_remap(blockIdx.x, gridDim.x) * wpb + wv;
     if (tile >= g.n_tiles) return;
     if constexpr (CUBE != 0)
-        tile3d_cube<M, R, KW, CUBE == 2>(g, tile, smem + (size_t)wv * tile3d_lds_per_wave<M, 2>(R));
+        tile3d_cube<M, R, KW, CUBE == 2>(g, tile, smem + (size_t)wv * cube_lds_per_wave<M>(R));
     else
         tile3d<M, R, KW, TY, VEC>(g, tile, smem + (size_t)wv * tile3d_lds_per_wave<M, TY>(R));
 }

@@ -9,14 +9,15 @@ static hipError_t go3(const P3D& g, bool vec, int cube, int grid, int wpb, hipSt
 {
     const size_t smem = (size_t)wpb * tile3d_lds_per_wave<MODE_U16, TY>(4);
     if constexpr (TY == 2) {
+        const size_t smemc = (size_t)wpb * cube_lds_per_wave<MODE_U16>(4);
         if (cube == 2 && vec) {
             hipLaunchKernelGGL((corr3d_kernel<MODE_U16, 4, KW, 2, true, 2>), dim3(grid),
-                               dim3(wpb * kWave), smem, s, g);
+                               dim3(wpb * kWave), smemc, s, g);
             return hipGetLastError();
         }
         if (cube == 1 && vec) {
             hipLaunchKernelGGL((corr3d_kernel<MODE_U16, 4, KW, 2, true, 1>), dim3(grid),
-                               dim3(wpb * kWave), smem, s, g);
+                               dim3(wpb * kWave), smemc, s, g);
             return hipGetLastError();
         }
     }
