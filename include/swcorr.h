@@ -211,7 +211,8 @@ swc_status swc_host_plan_create(const swc_problem *p, int64_t band_rows, int32_t
  * memory works but serialises them.  Synchronous: returns once c and flags
  * hold the result (all streams drained, also after an error).  Results equal
  * swc_corr's on the whole array (bit-exact for integer input; float input
- * within the same bound, since the slabs are tiled differently). */
+ * within the same bound, since the slabs are tiled differently).  The device
+ * current at plan creation must be current (SWC_ERR_DEVICE otherwise). */
 swc_status swc_host_run(swc_host_plan *plan, const void *x, const void *y, float *c,
                         uint8_t *flags);
 /* Number of slabs per run. */
@@ -265,7 +266,8 @@ swc_status swc_batch_plan_create(int32_t n, const swc_problem *p, const void *co
                                  uint8_t *const *flags, const swc_launch_params *lp,
                                  swc_batch_plan **out);
 
-/* Compute every pair of the plan on `stream`: persistent launches, one per
+/* Compute every pair of the plan on `stream` (the device current at plan
+ * creation must be current; SWC_ERR_DEVICE otherwise): persistent launches, one per
  * group of pairs whose LDS rings allow the same number of resident
  * wavefronts per CU (at most four), plus one ordinary launch per pair without
  * a compiled window width.  Asynchronous, allocates nothing, safe to capture

@@ -352,6 +352,9 @@ swc_status swc_batch_plan_create(int32_t n, const swc_problem* p, const void* co
 swc_status swc_batch_launch(const swc_batch_plan* plan, void* stream)
 {
     if (!plan) return SWC_ERR_NULL;
+    // the work lists live on the plan's device
+    int cur = -1;
+    if (hipGetDevice(&cur) != hipSuccess || cur != plan->device) return SWC_ERR_DEVICE;
     hipStream_t s = (hipStream_t)stream;
     for (const BatchGroup& G : plan->groups) {
         const int grid = (int)((G.nwaves + G.wpb - 1) / G.wpb);

@@ -30,6 +30,7 @@ struct swc_host_plan {
     int64_t in_row;        // input elements per first-axis index
     int64_t out_row;       // output elements per first-axis index
     size_t esz;
+    int device;            // the device current at creation (owns the buffers)
     std::vector<hipStream_t> streams;
     std::vector<void*> dx, dy, dc, df;   // per stream: staging buffers
 };
@@ -90,8 +91,11 @@ swc_status swc_host_plan_create(const swc_problem* p, int64_t band_rows, int32_t
     *out = nullptr;
     if (p->step[0] != 1) return SWC_ERR_UNSUPPORTED;
     if (band_rows < 1 || depth < 1 || depth > 8) return SWC_ERR_PARAM;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return SWC_ERR_DEVICE;
     swc_host_plan* P = new swc_host_plan();
     P->p = *p;
+    P->device = dev;
     swc_output_shape(p, P->oshape);
     P->band = band_rows < P->oshape[0] ? band_rows : P->oshape[0];
     P->depth = depth;
@@ -140,6 +144,9 @@ swc_status swc_host_run(swc_host_plan* P, const void* x, const void* y, float* c
                         uint8_t* flags)
 {
     if (!P || !x || !y || !c) return SWC_ERR_NULL;
+    // the staging buffers and streams belong to the plan's device
+    int cur = -1;
+    if (hipGetDevice(&cur) != hipSuccess || cur != P->device) return SWC_ERR_DEVICE;
     const int64_t OH = P->oshape[0];
     const size_t ib = (size_t)P->in_row * P->esz;
     const size_t ob = (size_t)P->out_row;
