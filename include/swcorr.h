@@ -285,9 +285,11 @@ void swc_batch_plan_destroy(swc_batch_plan *plan);
 
 /* Bit 0: send every integer-input output through the exact big-integer
  * rounding decision and every float-input output through the two-pass
- * window recomputation (results must not change).  Host only; applies to
- * launches issued after the call.  Also set from SWC_FORCE_EXACT_FALLBACK=1
- * at library load. */
+ * window recomputation (results must not change).  Bit 1: 2-D pairs use the
+ * generic LDS-row kernel and 3-D problems the general step.  Bit 2: the 1-D
+ * kernel re-reads the values leaving the window from memory instead of its
+ * LDS ring.  Host only; applies to launches issued after the call.  Bit 0 is
+ * also set from SWC_FORCE_EXACT_FALLBACK=1 at library load. */
 void swc_set_debug(int32_t bits);
 int32_t swc_get_debug(void);
 

@@ -345,7 +345,9 @@ swc_status swc_corr_ex(const swc_problem* p, const swc_launch_params* lp, const 
         (void)hipGetLastError();
     }
     hipError_t e;
-    const int force = g_debug & 3;   // bit 0: exact fallbacks, bit 1: generic kernel
+    // bit 0: exact fallbacks; bit 1: generic 2-D kernel / general 3-D step;
+    // bit 2: 1-D re-reads leaving values instead of its LDS ring
+    const int force = g_debug & 7;
     if (p->ndim == 1) e = launch_corr1d(*p, osh, L, x, y, c, flags, s, force);
     else if (p->ndim == 2) e = launch_corr2d(*p, osh, L, x, y, c, flags, s, force);
     else e = launch_corr3d(*p, osh, L, x, y, c, flags, s, force);

@@ -36,6 +36,7 @@ struct P1D {
     int64_t seg;          // outputs per wave
     int64_t n_waves;
     int vst;              // output base 16-byte aligned: whole-vector stores allowed
+    int ring_g;           // RING kernel: groups of 8 positions in the per-wave LDS ring
 };
 
 constexpr int kR1 = 8;    // positions per lane per row
@@ -199,7 +200,13 @@ template <int R> struct Row1 {
 // per-lane state) are left to the compiler.
 template <int M> constexpr int corr1d_min_waves() { return M == MODE_F64 ? 2 : 1; }
 
-template <int M>
+// RING: the values leaving the window come from a per-wave LDS ring of the
+// last ring_g*8 positions instead of a second read from memory.  Position p
+// lives at word (p mod 8) * ring_g + (p / 8 mod ring_g): a lane owns 8
+// consecutive positions starting at a multiple of 8, so for each of its 8
+// elements the 64 lanes write, and (shifted back by k) read, 64 consecutive
+// words.  The ring holds the raw values; missing values are masked on use.
+template <int M, bool RING>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(corr1d_min_waves<M>(), 8)))
 corr1d_kernel(P1D g)
 {
@@ -229,11 +236,24 @@ corr1d_kernel(P1D g)
     const SpanBuf by = span_buf<T>((const T*)g.y, N, e_base);
     const int pstep = g.s;
 
+    // ---- per-wave LDS ring (RING) ----
+    extern __shared__ float ring_smem[];
+    const int rg = g.ring_g;
+    float* ringx = ring_smem + (size_t)wv * 2 * 8 * rg;
+    float* ringy = ringx + 8 * rg;
+    auto ring_at = [&](int p) __attribute__((always_inline)) {
+        return (p & 7) * rg + ((p >> 3) & (rg - 1));
+    };
+
     // ---- carry = sums over span positions [kal - k, kal - 1] ----
     Ch<M> part = ch_zero<M>();
     float mx = 0.f, my = 0.f;
     for (int i = kal - k + lane; i < kal; i += kWave) {
         float a = span_load<T>(bx, i), b = span_load<T>(by, i);
+        if constexpr (RING) {
+            ringx[ring_at(i)] = a;
+            ringy[ring_at(i)] = b;
+        }
         int m = 0;
         if constexpr (kFloat) {
             // positions outside the series read zero and are never missing
@@ -271,12 +291,28 @@ corr1d_kernel(P1D g)
         const bool whole_out = (d0 - k >= dmin) && (d0 - k + R - 1 < nlim);
         span_load_run<T, R>(bx, d0, whole_in, r.a);
         span_load_run<T, R>(by, d0, whole_in, r.b);
-        span_load_run<T, R>(bx, d0 - k, whole_out, r.ao);
-        span_load_run<T, R>(by, d0 - k, whole_out, r.bo);
+        if constexpr (!RING) {
+            span_load_run<T, R>(bx, d0 - k, whole_out, r.ao);
+            span_load_run<T, R>(by, d0 - k, whole_out, r.bo);
+        }
     };
 
     auto process = [&](int rrel, Row1<R>& r) __attribute__((always_inline)) {
         const int d0 = rrel + lane * R;
+        if constexpr (RING) {
+            // park the entering row, then read the leaving one (it may lie in
+            // this row when k < 64*R; a wave's LDS accesses complete in order)
+#pragma unroll
+            for (int j = 0; j < R; j++) {
+                ringx[ring_at(d0 + j)] = r.a[j];
+                ringy[ring_at(d0 + j)] = r.b[j];
+            }
+#pragma unroll
+            for (int j = 0; j < R; j++) {
+                r.ao[j] = ringx[ring_at(d0 + j - k)];
+                r.bo[j] = ringy[ring_at(d0 + j - k)];
+            }
+        }
         int m[R], mo[R];
         float lmx = 0.f, lmy = 0.f;
 #pragma unroll
@@ -531,7 +567,12 @@ bool cfg_ok_1d(const swc_problem& p, const LaunchCfg& L)
 template <int M>
 static hipError_t go1d(const P1D& g, int grid, int wpb, hipStream_t s)
 {
-    hipLaunchKernelGGL((corr1d_kernel<M>), dim3(grid), dim3(wpb * kWave), 0, s, g);
+    if (g.ring_g > 0) {
+        const size_t smem = (size_t)wpb * 2 * 8 * g.ring_g * sizeof(float);
+        hipLaunchKernelGGL((corr1d_kernel<M, true>), dim3(grid), dim3(wpb * kWave), smem, s, g);
+    } else {
+        hipLaunchKernelGGL((corr1d_kernel<M, false>), dim3(grid), dim3(wpb * kWave), 0, s, g);
+    }
     return hipGetLastError();
 }
 
@@ -562,6 +603,14 @@ hipError_t launch_corr1d(const swc_problem& p, const int64_t* oshape, const Laun
     const double rows = (double)(g.seg * g.s) / (kWave * kR1) + 1.0;
     const double chain = 2.0 * (double)(g.seg * g.s + g.k) + 16.0 * rows + 64.0;
     g.cert_g = cert_factor(mode, (double)g.k, chain, (double)g.k + 3.0);
+    // LDS ring of the leaving values: a power-of-two number of 8-position
+    // groups covering k + one row, at most 32 KB per wave (else re-read)
+    g.ring_g = 0;
+    {
+        int64_t need = ((int64_t)g.k + kWave * kR1 + 7) / 8, rg = 1;
+        while (rg < need) rg <<= 1;
+        if (rg * 8 * 2 * (int64_t)sizeof(float) <= 32 * 1024 && !(force & 4)) g.ring_g = (int)rg;
+    }
     const int64_t grid64 = (g.n_waves + L.wpb - 1) / L.wpb;
     if (grid64 >= ((int64_t)1 << 31)) return hipErrorInvalidValue;
     switch (mode) {

@@ -79,3 +79,29 @@ def test_parity_long_series_full_sampled():
                                     np.arange(n - 500, n)]))
     d = compare(x, y, (1001,), 1, "clip", indices=idx, tag="c4b-full")
     say(f"c4b full (sampled) max|dc| = {d:.3e}")
+
+
+@pytest.mark.parametrize("dtype", ["u8", "u16", "f32"])
+def test_parity_1d_ring_and_reread_paths(dtype):
+    """Leaving values from the per-wave LDS ring (windows up to ~3500) and
+    re-read from memory (debug bit 2, and windows too wide for the ring):
+    both match the oracle; integer results are identical bit for bit."""
+    import paper_1807_06507_amd as swc
+    from gpu_util import gpu_corr
+    x, y = random_pair((70001,), dtype, seed=44)
+    for k in (1, 7, 100, 511, 512, 513, 1001, 3000, 3600):
+        if dtype == "u16" and k > 1448:
+            continue
+        for border in ("clip", "fill"):
+            compare(x, y, (k,), 1, border, tag="1d-ring")
+            a, fa = gpu_corr(x, y, (k,), 1, border)
+            swc.set_debug(4)
+            try:
+                b, fb = gpu_corr(x, y, (k,), 1, border)
+            finally:
+                swc.set_debug(0)
+            assert np.array_equal(fa, fb)
+            if dtype != "f32":
+                assert np.array_equal(a.view(np.uint32), b.view(np.uint32))
+    xs, ys = random_pair((30000,), dtype, seed=45)
+    compare(xs, ys, (257,), (3,), "clip", tag="1d-ring-step")
