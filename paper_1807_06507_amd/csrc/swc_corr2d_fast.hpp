@@ -187,33 +187,6 @@ template <class T, int R> struct Run {
     uint32_t y[NW];
 };
 
-// Issue the loads of one lane's run at row offset `roff` (elements).  VEC:
-// aligned vector loads from the per-lane base pointers; otherwise one load
-// per element from clamped columns.
-template <class T, int R, bool VEC>
-__device__ __forceinline__ void issue_run(const T* __restrict__ xl, const T* __restrict__ yl,
-                                          int64_t roff, const int (&cidx)[R], Run<T, R>& out)
-{
-    if constexpr (VEC) {
-        const T* px = (const T*)__builtin_assume_aligned(xl + roff, sizeof(T) * R);
-        const T* py = (const T*)__builtin_assume_aligned(yl + roff, sizeof(T) * R);
-        __builtin_memcpy(out.x, px, sizeof(T) * R);
-        __builtin_memcpy(out.y, py, sizeof(T) * R);
-    } else {
-        T vx[R], vy[R];
-#pragma unroll
-        for (int j = 0; j < R; j++) {
-            vx[j] = xl[roff + cidx[j]];
-            vy[j] = yl[roff + cidx[j]];
-        }
-        uint32_t wx[Run<T, R>::NW] = {}, wy[Run<T, R>::NW] = {};
-        __builtin_memcpy(wx, vx, sizeof(T) * R);
-        __builtin_memcpy(wy, vy, sizeof(T) * R);
-#pragma unroll
-        for (int i = 0; i < Run<T, R>::NW; i++) { out.x[i] = wx[i]; out.y[i] = wy[i]; }
-    }
-}
-
 #ifndef SWC_FAST2D_EPI_GROUP
 #define SWC_FAST2D_EPI_GROUP 1
 #endif

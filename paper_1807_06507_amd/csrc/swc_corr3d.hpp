@@ -124,20 +124,6 @@ template <int M> struct S3Slot {
         for (int i = 0; i < NDW; i++) base[i * kWave + lane] = w[i];
         (void)a;
     }
-    // add v and return the new running sum
-    __device__ __forceinline__ Col<M> add_get(int lane, const Col<M>& v) const
-    {
-        uint32_t w[NDW];
-#pragma unroll
-        for (int i = 0; i < NDW; i++) w[i] = base[i * kWave + lane];
-        Col<M> cur;
-        __builtin_memcpy(&cur, w, sizeof(Col<M>));
-        col_add<M>(cur, v);
-        __builtin_memcpy(w, &cur, sizeof(Col<M>));
-#pragma unroll
-        for (int i = 0; i < NDW; i++) base[i * kWave + lane] = w[i];
-        return cur;
-    }
     __device__ __forceinline__ Col<M> get(int lane) const
     {
         uint32_t w[NDW];
