@@ -16,8 +16,8 @@ import os
 import threading
 
 __all__ = [
-    "Problem", "LaunchParams", "corr", "corr_into", "output_shape", "validate", "status_str",
-    "tune_set", "tune_get", "set_debug", "get_debug", "BatchPlan", "library_path",
+    "Problem", "LaunchParams", "corr", "corr_into", "prepare", "output_shape", "validate",
+    "status_str", "tune_set", "tune_get", "set_debug", "get_debug", "BatchPlan", "library_path",
     "SwcError", "FLAG_BORDER", "FLAG_MISSING", "FLAG_ZVAR_X", "FLAG_ZVAR_Y",
     "HostPlan", "corr_scheme", "scheme_workspace_bytes", "SCHEMES", "cloud_mask",
     "filter_detections",
@@ -245,6 +245,34 @@ def corr_into(p: Problem, x, y, out, flags=None, params=None, stream=None):
                            ctypes.c_void_p(out.data_ptr()), fptr, h)
     _check(code)
     return out
+
+
+def prepare(p: Problem, x, y, out, flags=None, params=None, stream=None):
+    """Check and marshal the arguments of ``corr_into`` once; returns a
+    callable that launches the same call again (asynchronously, on the same
+    stream) with no per-call Python work beyond the C call itself.  The
+    callable keeps the tensors alive."""
+    _check_tensor(x, "x")
+    _check_tensor(y, "y")
+    _check_tensor(out, "out")
+    if flags is not None:
+        _check_tensor(flags, "flags")
+    lib = _load()
+    lp = _params(params)
+    args = (ctypes.byref(p), ctypes.byref(lp) if lp is not None else None,
+            ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(y.data_ptr()),
+            ctypes.c_void_p(out.data_ptr()),
+            ctypes.c_void_p(flags.data_ptr()) if flags is not None else None,
+            _stream_handle(stream, x.device))
+    fn = lib.swc_corr_ex
+    keep = (p, lp, x, y, out, flags)
+
+    def launch():
+        code = fn(*args)
+        if code != 0:
+            _check(code)
+        return keep[4]
+    return launch
 
 
 def corr(x, y, window, step=1, border="fill", invalid=-2.0, missing_le=-999.0,

@@ -180,3 +180,26 @@ def test_register_and_lds_kernels_agree(dtype):
         if dtype != "f32":
             assert np.array_equal(a.view(np.uint32), b.view(np.uint32))
         compare(x, y, window, step, border, params=params, tag="fast-kernel")
+
+
+@pytest.mark.parametrize("dtype", ["u16", "f32"])
+def test_prepared_launch_equals_direct_call(dtype):
+    """A prepared launch (arguments marshalled once) gives the same map as the
+    direct call, on every repeat, with flags."""
+    import torch
+    import paper_1807_06507_amd as swc
+    from gpu_util import to_dev
+    x, y = random_pair((301, 1000), dtype, seed=43)
+    xd, yd = to_dev(x), to_dev(y)
+    ref, fref = swc.corr(xd, yd, (7, 7), 1, "clip", return_flags=True)
+    p = swc.make_problem(x.shape, xd.dtype, (7, 7), 1, "clip")
+    out = torch.full(ref.shape, 5.0, dtype=torch.float32, device="cuda")
+    fl = torch.full(ref.shape, 77, dtype=torch.uint8, device="cuda")
+    go = swc.prepare(p, xd, yd, out, fl)
+    for _ in range(3):
+        go()
+        torch.cuda.synchronize()
+        assert torch.equal(out.view(torch.int32), ref.view(torch.int32))
+        assert torch.equal(fl, fref)
+        out.fill_(5.0)
+        fl.fill_(77)
