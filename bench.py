@@ -12,9 +12,11 @@ more than twice that cache.
 
 Prints ONE JSON line (rank 0): metric, value (Gpixel/s of input processed),
 ms_per_step, roofline (HBM-bound; achieved = algorithmic bytes per launch /
-mean launch duration from HIP events around every launch in the timed
-region), and cpu_baseline (the CPU oracle timed on the host cores on a
-bounded sample of the same workload).
+mean launch duration, the time between two HIP events recorded on the launch
+stream around the K back-to-back launches of the timed region, over K), and
+cpu_baseline (the CPU oracle timed on the host cores on a bounded sample of
+the same workload).  A shorter pass with an event pair around every launch
+reports the spread of single launches.
 """
 from __future__ import annotations
 
@@ -174,6 +176,21 @@ def copy_ceiling(torch, nbytes=1 << 30, reps=20):
     return 2.0 * nbytes / (ms * 1e-3) / 1e9
 
 
+def _timed_region(torch, stream, n, fn):
+    """Run fn(i) for i < n back to back between one pair of HIP events on
+    `stream`; returns (wall seconds, mean ms per call from the events)."""
+    s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    s.record(stream)
+    for i in range(n):
+        fn(i)
+    e.record(stream)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    return elapsed, s.elapsed_time(e) / n
+
+
 def _timed(torch, stream, n, fn):
     """Run fn(i) for i < n with a HIP event pair around every launch on
     `stream`; returns (wall seconds, per-launch ms array)."""
@@ -263,23 +280,22 @@ def window_step_sweep(torch, swc, sets, dtype, w, stream, reps=20):
         for s in (1, 2, 4):
             p = swc.make_problem(w["shape"], dtype, (k, k), (s, s), w["border"])
             osh = swc.output_shape(p)
-            outs = [torch.empty(osh, dtype=torch.float32, device=sets[0][0].device)
-                    for _ in sets]
+            go = [swc.prepare(p, xd, yd, torch.empty(osh, dtype=torch.float32, device=xd.device),
+                              None, None, stream) for xd, yd, _ in sets]
 
             def run(i):
-                xd, yd, _ = sets[i % len(sets)]
-                swc.corr_into(p, xd, yd, outs[i % len(sets)], None, None, stream)
-            for i in range(3):
+                go[i % len(go)]()
+            for i in range(3 * len(go)):
                 run(i)
-            _, ms = _timed(torch, stream, reps, run)
-            t = float(ms.mean()) * 1e-3
+            _, ms = _timed_region(torch, stream, reps, run)
+            t = ms * 1e-3
             algo = in_bytes + int(np.prod(osh)) * 4
             res.append({"window": k, "step": s, "kernel_ms": round(t * 1e3, 5),
                         "gpix_s": round(n_in / t / 1e9, 2),
                         "out_pos_s": round(int(np.prod(osh)) / t / 1e9, 2),
                         "achieved_GBps": round(algo / t / 1e9, 1),
                         "frac": round(algo / t / 1e9 / HBM_PEAK_GBPS, 4)})
-            del outs
+            del go
     return res
 
 
@@ -297,7 +313,7 @@ def run_batched(args, torch, swc, dev):
     stream = torch.cuda.current_stream(dev)
     for _ in range(args.warmup):
         plan.launch()
-    elapsed, lms = _timed(torch, stream, args.steps, lambda i: plan.launch())
+    elapsed, mean_ms = _timed_region(torch, stream, args.steps, lambda i: plan.launch())
     probs = [swc.make_problem(tuple(d["x"].shape), d["x"].dtype, d["window"], 1, "clip")
              for d in dp]
 
@@ -308,15 +324,15 @@ def run_batched(args, torch, swc, dev):
         for f in singles:
             f()
     per_image(0)
-    e2, lms2 = _timed(torch, stream, max(3, args.steps // 4), per_image)
+    _, ms2 = _timed_region(torch, stream, max(3, args.steps // 4), per_image)
     g = torch.cuda.CUDAGraph()
     side = torch.cuda.Stream(device=dev)
     with torch.cuda.graph(g, stream=side):
         for pr, d, o in zip(probs, dp, plan.outputs):
             swc.corr_into(pr, d["x"], d["y"], o, None, None, torch.cuda.current_stream(dev))
     g.replay()
-    e3, lms3 = _timed(torch, stream, max(3, args.steps // 4), lambda i: g.replay())
-    mean_s = float(lms.mean()) * 1e-3
+    _, ms3 = _timed_region(torch, stream, max(3, args.steps // 4), lambda i: g.replay())
+    mean_s = mean_ms * 1e-3
     line = {
         "metric": METRIC, "value": round(args.steps * px / elapsed / 1e9, 3), "unit": "Gpixel/s",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
@@ -328,11 +344,10 @@ def run_batched(args, torch, swc, dev):
                      "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                      "frac": round(algo_bytes / mean_s / 1e9 / HBM_PEAK_GBPS, 4),
                      "traffic": None},
-        "kernel_ms_mean": round(float(lms.mean()), 5),
-        "kernel_ms_median": round(float(np.median(lms)), 5),
-        "per_image_launches_ms": round(float(lms2.mean()), 5),
-        "per_image_graph_ms": round(float(lms3.mean()), 5),
-        "batched_vs_per_image": round(float(lms2.mean()) / float(lms.mean()), 3),
+        "kernel_ms_mean": round(mean_ms, 5),
+        "per_image_launches_ms": round(ms2, 5),
+        "per_image_graph_ms": round(ms3, 5),
+        "batched_vs_per_image": round(ms2 / mean_ms, 3),
         "algorithmic_bytes_per_launch": algo_bytes,
         "kernel_source_hash": _kernel_source_hash("c3"),
     }
@@ -404,8 +419,12 @@ def main():
 
     for i in range(args.warmup):
         step(i)
-    elapsed, launch_ms = _timed(torch, stream, args.steps, step)
-    mean_launch_s = float(launch_ms.mean()) * 1e-3
+    # the timed region: K launches back to back between one event pair (the
+    # mean launch duration is the region's event time over K); then a shorter
+    # pass with an event pair around every launch for the spread
+    elapsed, mean_ms = _timed_region(torch, stream, args.steps, step)
+    mean_launch_s = mean_ms * 1e-3
+    _, launch_ms = _timed(torch, stream, min(args.steps, 100), step)
 
     n_in = int(np.prod(w["shape"]))
     value = args.steps * n_in / elapsed / 1e9
@@ -424,9 +443,11 @@ def main():
                    "step": list(w["step"]), "border": w["border"], "buffer_sets": n_sets,
                    "params": list(swc.tune_get(p)) if params is None else list(params)},
         "roofline": roof,
-        "kernel_ms_mean": round(float(launch_ms.mean()), 5),
-        "kernel_ms_median": round(float(np.median(launch_ms)), 5),
-        "kernel_ms_min": round(float(launch_ms.min()), 5),
+        "kernel_ms_mean": round(mean_ms, 5),
+        "per_launch_events": {"launches": int(launch_ms.size),
+                              "mean_ms": round(float(launch_ms.mean()), 5),
+                              "median_ms": round(float(np.median(launch_ms)), 5),
+                              "min_ms": round(float(launch_ms.min()), 5)},
         "algorithmic_bytes_per_launch": algo_bytes,
         "kernel_source_hash": khash,
     }
@@ -434,7 +455,7 @@ def main():
         line["window_step_sweep"] = window_step_sweep(torch, swc, sets, x.dtype, w, stream)
     if not args.no_schemes and len(w["shape"]) == 2 and tuple(w["step"]) == (1, 1):
         line["unfused_baselines"] = unfused_baselines(torch, swc, sets[0][0], sets[0][1], w,
-                                                      stream, float(launch_ms.mean()))
+                                                      stream, mean_ms)
     if not args.no_schemes and tuple(w["step"])[0] == 1:
         line["host_pipeline"] = host_pipeline(torch, swc, x, y, w)
     if not args.no_schemes:

@@ -34,7 +34,8 @@ def test_bench_line(cfg):
         assert isinstance(d[k], t), k
     assert d["n_gpus"] == 1 and d["steps"] == 3 and d["warmup"] == 1
     assert "workload" in d["config"] and "vs_baseline" in d
-    assert 0 < d["kernel_ms_min"] <= d["kernel_ms_median"]
+    ev = d["per_launch_events"]
+    assert 0 < ev["min_ms"] <= ev["median_ms"] and d["kernel_ms_mean"] > 0
     roof = d["roofline"]
     assert roof["bound"] == "hbm" and roof["unit"] == "GB/s" and roof["peak"] == 8000.0
     assert abs(roof["frac"] - roof["achieved"] / roof["peak"]) < 1e-3
