@@ -339,7 +339,8 @@ swc_status swc_corr_ex(const swc_problem* p, const swc_launch_params* lp, const 
     int64_t osh[3];
     swc_output_shape(p, osh);
     hipStream_t s = (hipStream_t)stream;
-    // a sticky error from earlier work would make the launch meaningless
+    // clear an error left by earlier, unrelated calls, so that the check
+    // after the launch reports this launch only
     hipError_t pre = hipPeekAtLastError();
     if (pre != hipSuccess) {
         (void)hipGetLastError();
