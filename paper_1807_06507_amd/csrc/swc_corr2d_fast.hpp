@@ -19,6 +19,8 @@
 // is computed once per tile; per-row quantities are wave-uniform.
 #pragma once
 
+#include <type_traits>
+
 #include "swc_device.hpp"
 
 namespace swc {
@@ -397,6 +399,8 @@ template <class T> __device__ __forceinline__ T opaque(T v)
 template <bool B> struct BoolTag {
     static constexpr bool value = B;
 };
+// Flag map chosen at run time (one code path for launches with and without).
+struct FlagsAtRuntime {};
 
 // Correctly rounded float32 of N / sqrt(q), q = Vx Vy, from exact integers
 // (q > 0): FP64 rsqrt estimate and one Newton step (relative error < 2^-38);
@@ -556,8 +560,14 @@ __device__ __forceinline__ void tile2d(const P2DF& g, const int tile, char* smem
     // ---- step 3-4 for output row p: window sums along the row, epilogue,
     //      store.  IN: the row and every output column of the tile are
     //      interior (full windows, no border handling). ----
-    auto out_row = [&](int p, auto in_tag, float (&cvals)[R], uint32_t (&flw)[(R + 3) / 4]) {
+    auto out_row = [&](int p, auto in_tag, auto fl_tag, float (&cvals)[R],
+                       uint32_t (&flw)[(R + 3) / 4]) {
         constexpr bool IN = decltype(in_tag)::value;
+        // a flag map is written: fixed by the tag, or the launch's choice
+        constexpr bool FL_RT = std::is_same<decltype(fl_tag), FlagsAtRuntime>::value;
+        bool FL = false;
+        if constexpr (FL_RT) FL = has_flags;
+        else FL = decltype(fl_tag)::value;
         const int rlo_w = p * g.sh + g.oh, rhi_w = rlo_w + kh - 1;
         const bool row_b = fill && (rlo_w < 0 || rhi_w >= H);
         uint32_t fillb_r = 0, ncolp_r[(R + 3) / 4] = {};
@@ -620,7 +630,7 @@ __device__ __forceinline__ void tile2d(const P2DF& g, const int tile, char* smem
                 cv = clamp_unit(__builtin_fma(0.5 * a0, e, a0));
                 bad = fb | (S.miss > 0);
                 pend = (!bad) & ((!cert) | force_exact);
-                if (has_flags) {
+                if (FL) {
                     const uint32_t fl = fb ? FL_BORDER : (S.miss > 0 ? FL_MISSING : 0);
                     flw[j / 4] |= fl << (8 * (j % 4));
                 }
@@ -630,7 +640,7 @@ __device__ __forceinline__ void tile2d(const P2DF& g, const int tile, char* smem
                 // Vx, Vy >= 0 are exact integers: a zero product is a zero variance
                 bad = fb | (q == 0.0);
                 pend = (!bad) & (amb | force_exact);
-                if (has_flags) {
+                if (FL) {
                     const uint32_t fl = fb ? FL_BORDER
                                            : ((Vx == 0.0 ? FL_ZVAR_X : 0u) | (Vy == 0.0 ? FL_ZVAR_Y : 0u));
                     flw[j / 4] |= fl << (8 * (j % 4));
@@ -689,19 +699,20 @@ __device__ __forceinline__ void tile2d(const P2DF& g, const int tile, char* smem
 
     // ---- stores of one step: buffer stores over an output row; columns
     //      that are not outputs of this tile carry an out-of-range offset,
-    //      and a step without an output row (or a launch without flags)
-    //      stores through a zero-length record.  Every step issues the same
-    //      stores, so the loads still in flight can be counted exactly when
-    //      the next row is waited for (stores share that counter). ----
-    auto store_row = [&](bool emit, int64_t orow_p, auto svec_tag, const float (&cvals)[R],
-                         const uint32_t (&flw)[(R + 3) / 4]) {
+    //      and a step without an output row stores through a zero-length
+    //      record.  Every step issues the same stores (flag stores only when
+    //      a flag map is written), so the loads still in flight can be
+    //      counted exactly when the next row is waited for (stores share
+    //      that counter). ----
+    auto store_row = [&](bool emit, int64_t orow_p, auto svec_tag, auto fl_tag,
+                         const float (&cvals)[R], const uint32_t (&flw)[(R + 3) / 4]) {
         constexpr bool SVEC = decltype(svec_tag)::value;
+        // run-time choice: flag stores go through a zero-length record when
+        // there is no map; compile-time choice: none are issued without one
+        constexpr bool RT = std::is_same<decltype(fl_tag), FlagsAtRuntime>::value;
         const int64_t orow = emit ? orow_p : 0;
         const __amdgpu_buffer_rsrc_t rc =
             __builtin_amdgcn_make_buffer_rsrc(g.c + orow, (short)0, emit ? g.OW * 4 : 0, kBufWord3);
-        const __amdgpu_buffer_rsrc_t rf = __builtin_amdgcn_make_buffer_rsrc(
-            has_flags ? (void*)(g.flags + orow) : (void*)g.c, (short)0,
-            (emit && has_flags) ? g.OW : 0, kBufWord3);
         if constexpr (SVEC) {
 #pragma unroll
             for (int j = 0; j < R; j += 4) {
@@ -709,18 +720,29 @@ __device__ __forceinline__ void tile2d(const P2DF& g, const int tile, char* smem
                            __float_as_uint(cvals[j + 2]), __float_as_uint(cvals[j + 3])};
                 __builtin_amdgcn_raw_buffer_store_b128(v, rc, voff + 4u * j, 0, 0);
             }
-#pragma unroll
-            for (int i = 0; i < R / 4; i++)
-                __builtin_amdgcn_raw_buffer_store_b32(flw[i], rf, vfoff + 4u * i, 0, 0);
         } else {
 #pragma unroll
             for (int j = 0; j < R; j++)
                 __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(cvals[j]), rc, qoff[j], 0, 0);
+        }
+        bool fl_store = true;
+        if constexpr (!RT) fl_store = decltype(fl_tag)::value;
+        if (fl_store) {
+            const bool on = RT ? has_flags : true;
+            const __amdgpu_buffer_rsrc_t rf = __builtin_amdgcn_make_buffer_rsrc(
+                on ? (void*)(g.flags + orow) : (void*)g.c, (short)0, (emit && on) ? g.OW : 0,
+                kBufWord3);
+            if constexpr (SVEC) {
 #pragma unroll
-            for (int j = 0; j < R; j++) {
-                const uint32_t qo = opaque(qoff[j]);
-                __builtin_amdgcn_raw_buffer_store_b8((uint8_t)(flw[j / 4] >> (8 * (j % 4))), rf,
-                                                     qo == kOffNone ? kOffNone : qo >> 2, 0, 0);
+                for (int i = 0; i < R / 4; i++)
+                    __builtin_amdgcn_raw_buffer_store_b32(flw[i], rf, vfoff + 4u * i, 0, 0);
+            } else {
+#pragma unroll
+                for (int j = 0; j < R; j++) {
+                    const uint32_t qo = opaque(qoff[j]);
+                    __builtin_amdgcn_raw_buffer_store_b8((uint8_t)(flw[j / 4] >> (8 * (j % 4))), rf,
+                                                         qo == kOffNone ? kOffNone : qo >> 2, 0, 0);
+                }
             }
         }
     };
@@ -730,7 +752,7 @@ __device__ __forceinline__ void tile2d(const P2DF& g, const int tile, char* smem
     // place in the loop body and the compiler can count the loads still in
     // flight when it waits for the oldest one.
     // ---- the march down the tile ----
-    auto march = [&](auto svec_tag) {
+    auto march = [&](auto svec_tag, auto fl_tag) {
         Run<T, R> pf[D];
         // rows are issued in order, one per step: keep the next row's index
         // and byte offset in scalar registers instead of recomputing them
@@ -860,11 +882,11 @@ __device__ __forceinline__ void tile2d(const P2DF& g, const int tile, char* smem
                     next_ready += g.sh;
                     const int rw = p * g.sh + g.oh;
                     if (cols_inside && rw >= 0 && rw + kh - 1 <= H - 1)
-                        out_row(p, BoolTag<true>{}, cvals, flw);
+                        out_row(p, BoolTag<true>{}, fl_tag, cvals, flw);
                     else
-                        out_row(p, BoolTag<false>{}, cvals, flw);
+                        out_row(p, BoolTag<false>{}, fl_tag, cvals, flw);
                 }
-                store_row(emit, orow, svec_tag, cvals, flw);
+                store_row(emit, orow, svec_tag, fl_tag, cvals, flw);
                 if (emit) {
                     p += pstep;
                     orow += orow_step;
@@ -873,11 +895,25 @@ __device__ __forceinline__ void tile2d(const P2DF& g, const int tile, char* smem
         }
     };
     // whole-vector stores for the tile (every output lane full, flags
-    // either absent or aligned as well)
-    if (tile_vec && (!has_flags || (g.vst & 2)))
-        march(BoolTag<true>{});
-    else
-        march(BoolTag<false>{});
+    // either absent or aligned as well).  Float input: separate code for
+    // launches with and without a flag map (without, no flag is formed or
+    // stored); integer input keeps one path, which measured faster there.
+    if constexpr (!kFloat) {
+        if (tile_vec && (!has_flags || (g.vst & 2)))
+            march(BoolTag<true>{}, FlagsAtRuntime{});
+        else
+            march(BoolTag<false>{}, FlagsAtRuntime{});
+    } else if (has_flags) {
+        if (tile_vec && (g.vst & 2))
+            march(BoolTag<true>{}, BoolTag<true>{});
+        else
+            march(BoolTag<false>{}, BoolTag<true>{});
+    } else {
+        if (tile_vec)
+            march(BoolTag<true>{}, BoolTag<false>{});
+        else
+            march(BoolTag<false>{}, BoolTag<false>{});
+    }
 }
 
 

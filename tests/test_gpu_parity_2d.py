@@ -203,3 +203,31 @@ def test_prepared_launch_equals_direct_call(dtype):
         assert torch.equal(fl, fref)
         out.fill_(5.0)
         fl.fill_(77)
+
+
+@pytest.mark.parametrize("dtype", ["u8", "u16", "f32"])
+def test_maps_with_and_without_flag_map_agree(dtype):
+    """Launches that write a flag map and launches that do not (float input
+    has separate code for each) give bit-identical coefficient maps,
+    including border, missing and constant windows, in vector-store and
+    per-column tiles."""
+    import torch
+    import paper_1807_06507_amd as swc
+    from gpu_util import to_dev
+    for shape, window, step, border in [((130, 1000), (7, 7), 1, "fill"),
+                                        ((97, 517), (5, 3), 1, "clip"),
+                                        ((64, 301), (7, 7), (2, 3), "valid")]:
+        x, y = random_pair(shape, dtype, seed=47)
+        if dtype == "f32":
+            x[5, 40] = -1000.0
+            y[60, 200] = np.nan
+            x[20:40, 100:160] = 3.0
+        else:
+            x[20:40, 100:160] = 9
+        xd, yd = to_dev(x), to_dev(y)
+        a, fl = swc.corr(xd, yd, window, step, border, return_flags=True)
+        b = swc.corr(xd, yd, window, step, border)
+        torch.cuda.synchronize()
+        say(f"flags/no-flags {dtype} {shape} {window} {step} {border}")
+        assert torch.equal(a.view(torch.int32), b.view(torch.int32))
+        assert int((fl != 0).sum()) > 0
