@@ -162,7 +162,8 @@ def main():
             emit("f32", 2, 0, kbucket(k), b[1])
     if only is None or "c3" in only:
         pairs = batched_pairs(64, seed=1)
-        candb = [(4, th, w) for th, w in itertools.product([0, 32, 64, 96, 128], [0, 1, 2])]
+        candb = [(4, th, w) for th, w in itertools.product([0, 16, 24, 32, 40, 48, 64, 96, 128],
+                                                           [0, 1, 2])]
         b = tune_batch(pairs, candb, "f32 batch")
         emit("f32", 2, 0, 0, b[1])
     if only is None or "c4b" in only:
