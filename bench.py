@@ -343,7 +343,7 @@ def run_batched(args, torch, swc, dev):
         "roofline": {"bound": "hbm", "achieved": round(algo_bytes / mean_s / 1e9, 1),
                      "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                      "frac": round(algo_bytes / mean_s / 1e9 / HBM_PEAK_GBPS, 4),
-                     "traffic": None},
+                     "traffic": _traffic_from_profiles(_kernel_source_hash("c3"), "c3")},
         "kernel_ms_mean": round(mean_ms, 5),
         "per_image_launches_ms": round(ms2, 5),
         "per_image_graph_ms": round(ms3, 5),
