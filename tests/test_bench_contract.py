@@ -18,7 +18,7 @@ def test_more_than_one_gpu_is_refused():
 
 
 @pytest.mark.gpu
-@pytest.mark.parametrize("cfg", ["c1", "c4b"])
+@pytest.mark.parametrize("cfg", ["c1", "c3", "c4b"])
 def test_bench_line(cfg):
     r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--config", cfg,
                         "--steps", "3", "--warmup", "1", "--no-cpu", "--no-copy", "--no-schemes"],
@@ -34,8 +34,12 @@ def test_bench_line(cfg):
         assert isinstance(d[k], t), k
     assert d["n_gpus"] == 1 and d["steps"] == 3 and d["warmup"] == 1
     assert "workload" in d["config"] and "vs_baseline" in d
-    ev = d["per_launch_events"]
-    assert 0 < ev["min_ms"] <= ev["median_ms"] and d["kernel_ms_mean"] > 0
+    assert d["kernel_ms_mean"] > 0
+    if cfg == "c3":
+        assert d["batched_vs_per_image"] > 0 and d["config"]["pairs"] == 64
+    else:
+        ev = d["per_launch_events"]
+        assert 0 < ev["min_ms"] <= ev["median_ms"]
     roof = d["roofline"]
     assert roof["bound"] == "hbm" and roof["unit"] == "GB/s" and roof["peak"] == 8000.0
     assert abs(roof["frac"] - roof["achieved"] / roof["peak"]) < 1e-3
