@@ -209,3 +209,19 @@ def test_mask_argument_errors(lib):
     assert lib.swc_filter_detections(fake, None, 10, fake, -1, 0.5, -2.0, fake, None) == 3
     assert lib.swc_filter_detections(fake, None, 10, None, 5, 0.5, -2.0, fake, None) == 1
     assert lib.swc_filter_detections(None, None, 10, None, 0, 0.5, -2.0, None, None) == 0
+
+
+def test_binding_rejects_host_tensors_before_any_launch(lib):
+    """The binding takes device tensors only: host tensors are refused with a
+    clear error by the direct call and by a prepared launch alike (there is no
+    CPU path to fall back to)."""
+    import torch
+    x = torch.zeros((8, 8), dtype=torch.uint16)
+    out = torch.zeros((8, 8), dtype=torch.float32)
+    p = swc.make_problem((8, 8), x.dtype, (3, 3), 1, "fill")
+    with pytest.raises(ValueError, match="GPU"):
+        swc.prepare(p, x, x, out)
+    with pytest.raises(ValueError, match="GPU"):
+        swc.corr_into(p, x, x, out)
+    with pytest.raises(ValueError, match="GPU"):
+        swc.corr(x, x, (3, 3))
