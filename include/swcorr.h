@@ -34,7 +34,15 @@
  * Error behaviour: every entry point validates its arguments first and
  * returns an error code without touching any memory or launching anything
  * when they are invalid.  Nothing here aborts, throws or prints (unless the
- * environment variable SWC_LOG=1 asks for host-side debug output).
+ * environment variable SWC_LOG=1 asks for host-side debug output).  A launch
+ * reports its own status (SWC_ERR_LAUNCH when the runtime refuses it); a
+ * device fault left pending by earlier work (an error after which the device
+ * runs nothing) gives SWC_ERR_DEVICE before anything is launched.  Other
+ * errors pending in the HIP runtime are left untouched for whoever caused
+ * them.  With SWC_FAULT_INJECT=launch in the environment when the library
+ * initialises, every entry point that would launch device work returns
+ * SWC_ERR_LAUNCH instead, without touching the device (for tests of error
+ * propagation).
  */
 #ifndef SWCORR_H
 #define SWCORR_H
@@ -288,8 +296,12 @@ void swc_batch_plan_destroy(swc_batch_plan *plan);
  * window recomputation (results must not change).  Bit 1: 2-D pairs use the
  * generic LDS-row kernel and 3-D problems the general step.  Bit 2: the 1-D
  * kernel re-reads the values leaving the window from memory instead of its
- * LDS ring.  Host only; applies to launches issued after the call.  Bit 0 is
- * also set from SWC_FORCE_EXACT_FALLBACK=1 at library load. */
+ * LDS ring.  Bit 3: the compensated float32 comparator (SWC_ACC_COMP_F32)
+ * skips its certification test, so every window with a positive computed
+ * variance takes the value of its compensated sums (measures those sums'
+ * own accuracy; constant windows still get their flags).  Host only;
+ * applies to launches issued after the call.  Bit 0 is also set from
+ * SWC_FORCE_EXACT_FALLBACK=1 at library load. */
 void swc_set_debug(int32_t bits);
 int32_t swc_get_debug(void);
 

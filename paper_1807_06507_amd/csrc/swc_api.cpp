@@ -42,12 +42,23 @@ float missing_threshold(double t)
 
 double cert_factor(int mode, double n, double chain, double nterms)
 {
-    // unit roundoff of the sliding sums: FP64 for the default float mode,
-    // a conservative 2^-44 for compensated FP32 pairs
-    const double u = (mode == 4) ? ldexp(1.0, -44) : ldexp(1.0, -53);
+    // unit roundoff of the sliding sums.  FP64 sums: 2^-53 per operation.
+    // Compensated FP32 pairs (hi, lo): every TwoSum is exact, its error term
+    // is at most 2^-24 of the partial sum, so |lo| stays below 2 C 2^-24 P
+    // over a chain of C operations on partial sums bounded by P (product
+    // tails included), and each of the 2C roundings of lo costs at most
+    // 2^-24 |lo|: in all 4 C^2 2^-48 P, i.e. a per-operation roundoff of
+    // C 2^-46 in the bound below
+    const double u = (mode == 4) ? chain * ldexp(1.0, -46) : ldexp(1.0, -53);
     const double rho = 4096.0;   // fast path only when |dc| <= 2/(rho-1)
     const double g = u * n * (3.0 * chain * nterms + 6.0 * n) * (1.0 + ldexp(1.0, -10));
     return rho * g;
+}
+
+swc_status launch_status(hipError_t e)
+{
+    if (e == hipSuccess) return SWC_OK;
+    return sticky_error(e) ? SWC_ERR_DEVICE : SWC_ERR_LAUNCH;
 }
 
 }  // namespace swc
@@ -61,6 +72,7 @@ constexpr int64_t kMaxWindowU16 = 1448;    // n^2 (2^16-1)^2 < 2^53
 constexpr int64_t kMaxWindowU8 = 33025;    // n (2^8-1)^2 < 2^31
 
 int g_debug = 0;
+bool g_fault_launch = false;
 std::once_flag g_init_once;
 std::mutex g_tune_mu;
 std::map<std::tuple<int, int, int, int>, swc_launch_params> g_tune;
@@ -110,6 +122,8 @@ void init_once()
     g_log = lg && lg[0] == '1';
     const char* fe = getenv("SWC_FORCE_EXACT_FALLBACK");
     if (fe && fe[0] == '1') g_debug |= 1;
+    const char* fi = getenv("SWC_FAULT_INJECT");
+    g_fault_launch = fi && strcmp(fi, "launch") == 0;
     // tuning table: SWC_TUNE_TABLE, else tune_table.txt next to the library
     const char* tt = getenv("SWC_TUNE_TABLE");
     std::lock_guard<std::mutex> lk(g_tune_mu);
@@ -193,6 +207,12 @@ LaunchCfg resolve_cfg(const swc_problem* p)
 }  // namespace
 
 namespace swc {
+bool fault_inject_launch()
+{
+    ensure_init();
+    return g_fault_launch;
+}
+
 // Launch configuration of one pair computed outside a persistent batch.
 LaunchCfg batch_pair_cfg(const swc_problem& p) { return resolve_cfg(&p); }
 
@@ -339,25 +359,22 @@ swc_status swc_corr_ex(const swc_problem* p, const swc_launch_params* lp, const 
     int64_t osh[3];
     swc_output_shape(p, osh);
     hipStream_t s = (hipStream_t)stream;
-    // clear an error left by earlier, unrelated calls, so that the check
-    // after the launch reports this launch only
-    hipError_t pre = hipPeekAtLastError();
-    if (pre != hipSuccess) {
-        (void)hipGetLastError();
-    }
+    if (fault_inject_launch()) return SWC_ERR_LAUNCH;
+    // a device fault left by earlier work makes every launch fail: report it
+    // as such (without clearing it; other pending errors belong to whoever
+    // caused them, and launches report their own status)
+    if (sticky_error(hipPeekAtLastError())) return SWC_ERR_DEVICE;
     hipError_t e;
     // bit 0: exact fallbacks; bit 1: generic 2-D kernel / general 3-D step;
-    // bit 2: 1-D re-reads leaving values instead of its LDS ring
-    const int force = g_debug & 7;
+    // bit 2: 1-D re-reads leaving values instead of its LDS ring; bit 3: the
+    // compensated comparator skips its certification
+    const int force = g_debug & 15;
     if (p->ndim == 1) e = launch_corr1d(*p, osh, L, x, y, c, flags, s, force);
     else if (p->ndim == 2) e = launch_corr2d(*p, osh, L, x, y, c, flags, s, force);
     else e = launch_corr3d(*p, osh, L, x, y, c, flags, s, force);
     if (e != hipSuccess) {
         if (g_log) fprintf(stderr, "[swcorr] launch failed: %s\n", hipGetErrorString(e));
-        return (e == hipErrorInvalidValue || e == hipErrorInvalidConfiguration ||
-                e == hipErrorLaunchFailure)
-                   ? SWC_ERR_LAUNCH
-                   : SWC_ERR_DEVICE;
+        return launch_status(e);
     }
     if (g_log)
         fprintf(stderr, "[swcorr] ndim=%d dtype=%d R=%d TH=%d wpb=%d\n", p->ndim, p->dtype, L.R,
@@ -378,8 +395,10 @@ swc_status swc_cloud_mask(const float* c, const uint8_t* flags, int64_t n, float
     if (isnan(tau)) return SWC_ERR_PARAM;
     if (n == 0) return SWC_OK;
     if (!c || !mask) return SWC_ERR_NULL;
+    if (fault_inject_launch()) return SWC_ERR_LAUNCH;
+    if (sticky_error(hipPeekAtLastError())) return SWC_ERR_DEVICE;
     hipError_t e = launch_cloud_mask(c, flags, n, tau, invalid_value, mask, (hipStream_t)stream);
-    return e == hipSuccess ? SWC_OK : SWC_ERR_LAUNCH;
+    return launch_status(e);
 }
 
 swc_status swc_filter_detections(const float* c, const uint8_t* flags, int64_t n,
@@ -390,9 +409,11 @@ swc_status swc_filter_detections(const float* c, const uint8_t* flags, int64_t n
     if (isnan(tau)) return SWC_ERR_PARAM;
     if (k == 0) return SWC_OK;
     if (!idx || !keep || (n > 0 && !c)) return SWC_ERR_NULL;
+    if (fault_inject_launch()) return SWC_ERR_LAUNCH;
+    if (sticky_error(hipPeekAtLastError())) return SWC_ERR_DEVICE;
     hipError_t e = launch_filter_detections(c, flags, n, idx, k, tau, invalid_value, keep,
                                             (hipStream_t)stream);
-    return e == hipSuccess ? SWC_OK : SWC_ERR_LAUNCH;
+    return launch_status(e);
 }
 
 swc_status swc_scheme_workspace(const swc_problem* p, int32_t scheme, uint64_t* bytes)
@@ -416,16 +437,13 @@ swc_status swc_corr_scheme(const swc_problem* p, int32_t scheme, const void* x, 
     if (workspace_bytes < scheme_workspace_bytes(*p, scheme) || ((uintptr_t)workspace % 8) != 0)
         return SWC_ERR_WORKSPACE;
     ensure_init();
-    hipError_t pre = hipPeekAtLastError();
-    if (pre != hipSuccess) (void)hipGetLastError();
+    if (fault_inject_launch()) return SWC_ERR_LAUNCH;
+    if (sticky_error(hipPeekAtLastError())) return SWC_ERR_DEVICE;
     hipError_t e = launch_scheme(*p, scheme, x, y, c, flags, workspace, (hipStream_t)stream,
                                  g_debug & 1);
     if (e != hipSuccess) {
         if (g_log) fprintf(stderr, "[swcorr] scheme launch failed: %s\n", hipGetErrorString(e));
-        return (e == hipErrorInvalidValue || e == hipErrorInvalidConfiguration ||
-                e == hipErrorLaunchFailure)
-                   ? SWC_ERR_LAUNCH
-                   : SWC_ERR_DEVICE;
+        return launch_status(e);
     }
     return SWC_OK;
 }

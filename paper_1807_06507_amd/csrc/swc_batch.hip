@@ -302,7 +302,8 @@ swc_status swc_batch_plan_create(int32_t n, const swc_problem* p, const void* co
         g.tiles_y = (int)((osh[0] + TH - 1) / TH);
         g.n_tiles = tiles_x * g.tiles_y;
         const double th_ext = (double)(TH - 1) * q.step[0] + q.window[0];
-        const double chain = 2.0 * th_ext + q.window[1] + 2.0 * kBatchR + 2.0;
+        // same chain as the single-pair launch of this tile code
+        const double chain = 2.0 * th_ext + 2.0 * q.window[1] + 2.0 * kBatchR + 2.0;
         g.cert_g = cert_factor(mode, (double)q.window[0] * q.window[1], chain,
                                (double)(q.window[0] + 1) * (q.window[1] + 1));
         b.tile0 = tile0;
@@ -355,32 +356,35 @@ swc_status swc_batch_launch(const swc_batch_plan* plan, void* stream)
     // the work lists live on the plan's device
     int cur = -1;
     if (hipGetDevice(&cur) != hipSuccess || cur != plan->device) return SWC_ERR_DEVICE;
+    if (fault_inject_launch()) return SWC_ERR_LAUNCH;
+    if (sticky_error(hipPeekAtLastError())) return SWC_ERR_DEVICE;
     hipStream_t s = (hipStream_t)stream;
     for (const BatchGroup& G : plan->groups) {
         const int grid = (int)((G.nwaves + G.wpb - 1) / G.wpb);
         const size_t smem = (size_t)G.lds_stride * G.wpb;
         const dim3 blk(G.wpb * kWave);
+        hipError_t e;
         switch (plan->mode) {
         case MODE_U8:
-            hipLaunchKernelGGL((corr2d_batch_kernel<MODE_U8>), dim3(grid), blk, smem, s,
-                               G.d_items, G.n_items, G.total_tiles, G.nwaves, G.lds_stride);
+            e = launch_kernel(&corr2d_batch_kernel<MODE_U8>, dim3(grid), blk, smem, s, G.d_items,
+                              G.n_items, G.total_tiles, G.nwaves, G.lds_stride);
             break;
         case MODE_U16:
-            hipLaunchKernelGGL((corr2d_batch_kernel<MODE_U16>), dim3(grid), blk, smem, s,
-                               G.d_items, G.n_items, G.total_tiles, G.nwaves, G.lds_stride);
+            e = launch_kernel(&corr2d_batch_kernel<MODE_U16>, dim3(grid), blk, smem, s, G.d_items,
+                              G.n_items, G.total_tiles, G.nwaves, G.lds_stride);
             break;
         default:
-            hipLaunchKernelGGL((corr2d_batch_kernel<MODE_F64>), dim3(grid), blk, smem, s,
-                               G.d_items, G.n_items, G.total_tiles, G.nwaves, G.lds_stride);
+            e = launch_kernel(&corr2d_batch_kernel<MODE_F64>, dim3(grid), blk, smem, s, G.d_items,
+                              G.n_items, G.total_tiles, G.nwaves, G.lds_stride);
             break;
         }
-        if (hipGetLastError() != hipSuccess) return SWC_ERR_LAUNCH;
+        if (e != hipSuccess) return sticky_error(e) ? SWC_ERR_DEVICE : SWC_ERR_LAUNCH;
     }
     for (size_t i = 0; i < plan->rest_p.size(); i++) {
         hipError_t e = launch_corr2d(plan->rest_p[i], plan->rest_osh[i].data(), plan->rest_cfg[i],
                                      plan->rest_xy[i][0], plan->rest_xy[i][1], plan->rest_c[i],
                                      plan->rest_f[i], s, 0);
-        if (e != hipSuccess) return SWC_ERR_LAUNCH;
+        if (e != hipSuccess) return sticky_error(e) ? SWC_ERR_DEVICE : SWC_ERR_LAUNCH;
     }
     return SWC_OK;
 }

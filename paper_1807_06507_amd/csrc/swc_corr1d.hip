@@ -569,11 +569,9 @@ static hipError_t go1d(const P1D& g, int grid, int wpb, hipStream_t s)
 {
     if (g.ring_g > 0) {
         const size_t smem = (size_t)wpb * 2 * 8 * g.ring_g * sizeof(float);
-        hipLaunchKernelGGL((corr1d_kernel<M, true>), dim3(grid), dim3(wpb * kWave), smem, s, g);
-    } else {
-        hipLaunchKernelGGL((corr1d_kernel<M, false>), dim3(grid), dim3(wpb * kWave), 0, s, g);
+        return launch_kernel(&corr1d_kernel<M, true>, dim3(grid), dim3(wpb * kWave), smem, s, g);
     }
-    return hipGetLastError();
+    return launch_kernel(&corr1d_kernel<M, false>, dim3(grid), dim3(wpb * kWave), 0, s, g);
 }
 
 hipError_t launch_corr1d(const swc_problem& p, const int64_t* oshape, const LaunchCfg& L,

@@ -254,8 +254,7 @@ bool cfg_ok_2d(const swc_problem& p, const LaunchCfg& L)
 template <int M, int R>
 static hipError_t launch_mr(const P2D& g, int wpb, int grid, size_t smem, hipStream_t s)
 {
-    hipLaunchKernelGGL((corr2d_kernel<M, R>), dim3(grid), dim3(wpb * kWave), smem, s, g);
-    return hipGetLastError();
+    return launch_kernel(&corr2d_kernel<M, R>, dim3(grid), dim3(wpb * kWave), smem, s, g);
 }
 
 template <int M>
@@ -419,6 +418,9 @@ hipError_t launch_corr2d(const swc_problem& p, const int64_t* oshape, const Laun
     const double chain = 2.0 * th_ext + g.kw + 2.0 * ro * g.sw + 2.0;
     const double nterms = (double)(g.kh + 1) * (g.kw + 1);
     g.cert_g = cert_factor(mode, (double)g.kh * g.kw, chain, nterms);
+    // debug bit 3: the compensated comparator without its certification
+    // (a zero threshold passes every window of positive computed variance)
+    if (mode == MODE_F32C && (force & 8)) g.cert_g = 0.0;
     const int grid = (int)((nt + L.wpb - 1) / L.wpb);
     switch (mode) {
     case MODE_U8: return launch_m<MODE_U8>(g, L.R, L.wpb, grid, s);

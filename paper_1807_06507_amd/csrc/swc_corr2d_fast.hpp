@@ -354,6 +354,30 @@ __device__ __forceinline__ void hsum_onehop(const Col<M> (&V)[R], Emit&& emit)
     }
 }
 
+// Lanes a window sum of lane t reads: the columns -LH .. R-1+RH relative to
+// the lane's first column lie in lanes t - reach_l .. t + reach_r (the
+// one-hop form and the multi-hop slide reach the same lanes).
+template <int R, int KW> __host__ __device__ constexpr int reach_l() { return (KW / 2 + R - 1) / R; }
+template <int R, int KW> __host__ __device__ constexpr int reach_r()
+{
+    return (KW - 1 - KW / 2 + R - 1) / R;
+}
+
+// Max of a non-negative per-lane value over lanes t - reach_l .. t + reach_r
+// (each step widens the covered range by one lane; lanes past the wave's ends
+// contribute zero).
+template <int R, int KW> __device__ __forceinline__ float reach_max(float v)
+{
+    float ml = v, mr = v;
+#pragma unroll
+    for (int h = 0; h < reach_l<R, KW>(); h++)
+        ml = fmaxf(ml, __uint_as_float(dpp_from_left(__float_as_uint(ml))));
+#pragma unroll
+    for (int h = 0; h < reach_r<R, KW>(); h++)
+        mr = fmaxf(mr, __uint_as_float(dpp_from_right(__float_as_uint(mr))));
+    return fmaxf(ml, mr);
+}
+
 // Window sums of one output row, whichever form fits the window width.
 template <int M, int R, int KW, class Emit>
 __device__ __forceinline__ void hsum_row(const Col<M> (&V)[R], Emit&& emit)
@@ -582,10 +606,10 @@ __device__ __forceinline__ void tile2d(const P2DF& g, const int tile, char* smem
         const double dn_in = (double)(kh * KW);
         double gx = 0.0, gy = 0.0;   // certification thresholds (float input)
         if constexpr (kFloat) {
-            const double Mx = (double)fmaxf(hmx, fmaxf(__uint_as_float(dpp_from_left(__float_as_uint(hmx))),
-                                                __uint_as_float(dpp_from_right(__float_as_uint(hmx)))));
-            const double My = (double)fmaxf(hmy, fmaxf(__uint_as_float(dpp_from_left(__float_as_uint(hmy))),
-                                                __uint_as_float(dpp_from_right(__float_as_uint(hmy)))));
+            // M covers every column any window sum of this lane touched:
+            // the lanes t - reach_l .. t + reach_r
+            const double Mx = (double)reach_max<R, KW>(hmx);
+            const double My = (double)reach_max<R, KW>(hmy);
             gx = g.cert_g * Mx * Mx;
             gy = g.cert_g * My * My;
         }

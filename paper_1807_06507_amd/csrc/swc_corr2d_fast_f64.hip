@@ -11,8 +11,7 @@ static hipError_t go1(const P2DF& g, int grid, int wpb, size_t smem, hipStream_t
     if (occ)
         return hipOccupancyMaxActiveBlocksPerMultiprocessor(
             occ, corr2d_fast_kernel<MODE_F64, R, KW, VEC>, wpb * kWave, smem);
-    hipLaunchKernelGGL((corr2d_fast_kernel<MODE_F64, R, KW, VEC>), dim3(grid), dim3(wpb * kWave), smem, s, g);
-    return hipGetLastError();
+    return launch_kernel(&corr2d_fast_kernel<MODE_F64, R, KW, VEC>, dim3(grid), dim3(wpb * kWave), smem, s, g);
 }
 
 template <int R, int KW>

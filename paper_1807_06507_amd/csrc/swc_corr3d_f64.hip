@@ -11,23 +11,19 @@ static hipError_t go3(const P3D& g, bool vec, int cube, int grid, int wpb, hipSt
     if constexpr (TY == 2) {
         const size_t smemc = (size_t)wpb * cube_lds_per_wave<MODE_F64>(4);
         if (cube == 2 && vec) {
-            hipLaunchKernelGGL((corr3d_kernel<MODE_F64, 4, KW, 2, true, 2>), dim3(grid),
-                               dim3(wpb * kWave), smemc, s, g);
-            return hipGetLastError();
+            return launch_kernel(&corr3d_kernel<MODE_F64, 4, KW, 2, true, 2>, dim3(grid),
+                                 dim3(wpb * kWave), smemc, s, g);
         }
         if (cube == 1 && vec) {
-            hipLaunchKernelGGL((corr3d_kernel<MODE_F64, 4, KW, 2, true, 1>), dim3(grid),
-                               dim3(wpb * kWave), smemc, s, g);
-            return hipGetLastError();
+            return launch_kernel(&corr3d_kernel<MODE_F64, 4, KW, 2, true, 1>, dim3(grid),
+                                 dim3(wpb * kWave), smemc, s, g);
         }
     }
     if (vec)
-        hipLaunchKernelGGL((corr3d_kernel<MODE_F64, 4, KW, TY, true, 0>), dim3(grid),
-                           dim3(wpb * kWave), smem, s, g);
-    else
-        hipLaunchKernelGGL((corr3d_kernel<MODE_F64, 4, KW, TY, false, 0>), dim3(grid),
-                           dim3(wpb * kWave), smem, s, g);
-    return hipGetLastError();
+        return launch_kernel(&corr3d_kernel<MODE_F64, 4, KW, TY, true, 0>, dim3(grid),
+                             dim3(wpb * kWave), smem, s, g);
+    return launch_kernel(&corr3d_kernel<MODE_F64, 4, KW, TY, false, 0>, dim3(grid),
+                         dim3(wpb * kWave), smem, s, g);
 }
 
 template <int TY>

@@ -41,8 +41,12 @@ struct CF {
     float hi, lo;
 };
 __device__ __forceinline__ CF cf_zero() { return CF{0.f, 0.f}; }
+// Contraction is off in every compensated step: fusing a product into the
+// TwoSum (s = hi + a*a as one fma) would fold the exact product into s while
+// its TwoProd tail is still added to lo, counting the tail twice.
 __device__ __forceinline__ CF cf_add(CF a, float b)
 {
+#pragma clang fp contract(off)
     float s = a.hi + b;
     float bp = s - a.hi;
     float err = (a.hi - (s - bp)) + (b - bp);
@@ -50,6 +54,7 @@ __device__ __forceinline__ CF cf_add(CF a, float b)
 }
 __device__ __forceinline__ CF cf_add(CF a, CF b)
 {
+#pragma clang fp contract(off)
     CF t = cf_add(a, b.hi);
     t.lo += b.lo;
     return t;
@@ -161,7 +166,10 @@ __device__ __forceinline__ Elem<M> make_elem(typename Tr<M>::T vx, typename Tr<M
             e.x = a; e.y = b;
             e.xx = a * a; e.xy = a * b; e.yy = b * b;
         } else {
-            // compensated: exact products via FMA split (TwoProd)
+            // compensated: exact products via FMA split (TwoProd); the
+            // rounded products must stay rounded (no contraction into the
+            // sums that consume them)
+#pragma clang fp contract(off)
             float pxx = a * a, pxy = a * b, pyy = b * b;
             e.x = CF{a, 0.f};
             e.y = CF{b, 0.f};

@@ -5,9 +5,64 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <tuple>
+#include <type_traits>
+#include <utility>
+
 #include "swcorr.h"
 
 namespace swc {
+
+// Launch `k` on stream `s` and return the status of this launch itself, from
+// the launch call's own return value.  The runtime's per-thread "last error"
+// is neither read nor cleared, so an error that other work left pending stays
+// with its owner and is never reported as this launch's.
+template <typename... KArgs, typename... Args>
+inline hipError_t launch_kernel(void (*k)(KArgs...), dim3 grid, dim3 block, size_t smem,
+                                hipStream_t s, Args&&... args)
+{
+    static_assert(sizeof...(KArgs) == sizeof...(Args), "kernel argument count");
+    std::tuple<typename std::decay<KArgs>::type...> vals(std::forward<Args>(args)...);
+    return std::apply(
+        [&](auto&... v) {
+            void* argv[] = {(void*)&v...};
+            return hipLaunchKernel((const void*)k, grid, block, argv, smem, s);
+        },
+        vals);
+}
+
+// Evaluate a launch; return its status from the enclosing function on failure.
+#define SWC_TRY(expr)                       \
+    do {                                    \
+        const hipError_t swc_e_ = (expr);   \
+        if (swc_e_ != hipSuccess) return swc_e_; \
+    } while (0)
+
+// Errors after which the device cannot run further work (a fault in earlier
+// work on it): every later call fails with them.
+inline bool sticky_error(hipError_t e)
+{
+    switch (e) {
+    case hipErrorIllegalAddress:
+    case hipErrorLaunchFailure:
+    case hipErrorAssert:
+    case hipErrorLaunchTimeOut:
+    case hipErrorECCNotCorrectable:
+    case hipErrorContextIsDestroyed:
+        return true;
+    default:
+        return false;
+    }
+}
+
+// Injected failure for tests of error propagation: with SWC_FAULT_INJECT=launch
+// in the environment when the library initialises, every entry point that
+// would launch work returns SWC_ERR_LAUNCH instead, before touching the device.
+bool fault_inject_launch();
+
+// Status of a failed (or successful) launch: SWC_ERR_DEVICE for a sticky
+// device error, SWC_ERR_LAUNCH for any other failure.
+swc_status launch_status(hipError_t e);
 
 // Resolved launch configuration.
 struct LaunchCfg {

@@ -67,9 +67,8 @@ hipError_t launch_cloud_mask(const float* c, const uint8_t* flags, int64_t n, fl
     const int64_t groups = (n + 3) / 4;
     const int64_t blocks = (groups + 255) / 256;
     if (blocks >= ((int64_t)1 << 31)) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(cloud_mask_kernel, dim3((unsigned)blocks), dim3(256), 0, s, c, flags, n,
+    return launch_kernel(&cloud_mask_kernel, dim3((unsigned)blocks), dim3(256), 0, s, c, flags, n,
                        -tau, invalid, mask);
-    return hipGetLastError();
 }
 
 hipError_t launch_filter_detections(const float* c, const uint8_t* flags, int64_t n,
@@ -78,9 +77,8 @@ hipError_t launch_filter_detections(const float* c, const uint8_t* flags, int64_
 {
     const int64_t blocks = (k + 255) / 256;
     if (blocks >= ((int64_t)1 << 31)) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(filter_kernel, dim3((unsigned)blocks), dim3(256), 0, s, c, flags, n, idx,
+    return launch_kernel(&filter_kernel, dim3((unsigned)blocks), dim3(256), 0, s, c, flags, n, idx,
                        k, -tau, invalid, keep);
-    return hipGetLastError();
 }
 
 }  // namespace swc

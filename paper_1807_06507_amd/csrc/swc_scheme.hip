@@ -318,15 +318,14 @@ hipError_t launch_scheme(const swc_problem& p, int scheme, const void* x, const 
         uint64_t* I = (uint64_t*)ws;
         g.cert_g = 0.0;
         if (p.dtype == SWC_U8)
-            hipLaunchKernelGGL(cum_rows<uint8_t>, dim3(blocks_of(g.H, 64)), dim3(64), 0, s,
-                               (const uint8_t*)x, (const uint8_t*)y, I, plane, g.H, g.W);
+            SWC_TRY(launch_kernel(&cum_rows<uint8_t>, dim3(blocks_of(g.H, 64)), dim3(64), 0, s,
+                               (const uint8_t*)x, (const uint8_t*)y, I, plane, g.H, g.W));
         else
-            hipLaunchKernelGGL(cum_rows<uint16_t>, dim3(blocks_of(g.H, 64)), dim3(64), 0, s,
-                               (const uint16_t*)x, (const uint16_t*)y, I, plane, g.H, g.W);
-        hipLaunchKernelGGL(cum_cols, dim3(blocks_of(g.W, 64)), dim3(64), 0, s, I, plane, g.H, g.W);
-        hipLaunchKernelGGL(cum_final, dim3(nb), dim3(256), 0, s, (const uint64_t*)I, plane, g, c,
+            SWC_TRY(launch_kernel(&cum_rows<uint16_t>, dim3(blocks_of(g.H, 64)), dim3(64), 0, s,
+                               (const uint16_t*)x, (const uint16_t*)y, I, plane, g.H, g.W));
+        SWC_TRY(launch_kernel(&cum_cols, dim3(blocks_of(g.W, 64)), dim3(64), 0, s, I, plane, g.H, g.W));
+        return launch_kernel(&cum_final, dim3(nb), dim3(256), 0, s, (const uint64_t*)I, plane, g, c,
                            flags);
-        return hipGetLastError();
     }
     uint32_t* hdr = (uint32_t*)ws;
     double* E = (double*)((char*)ws + kHdrBytes);   // products, then window sums
@@ -337,29 +336,27 @@ hipError_t launch_scheme(const swc_problem& p, int scheme, const void* x, const 
     const double chain = 2.0 * g.W + 2.0 * g.H + 4.0;
     const double nterms = (double)(g.kh + 1) * (g.kw + 1);
     g.cert_g = cert_factor(MODE_F64, (double)g.kh * g.kw, chain, nterms);
-    hipLaunchKernelGGL(unf_init, dim3(1), dim3(64), 0, s, hdr);
+    SWC_TRY(launch_kernel(&unf_init, dim3(1), dim3(64), 0, s, hdr));
     if (p.dtype == SWC_U8)
-        hipLaunchKernelGGL((unf_products<uint8_t, false>), dim3(nb), dim3(256), 0, s,
-                           (const uint8_t*)x, (const uint8_t*)y, E, plane, thr, hdr);
+        SWC_TRY(launch_kernel(&unf_products<uint8_t, false>, dim3(nb), dim3(256), 0, s,
+                           (const uint8_t*)x, (const uint8_t*)y, E, plane, thr, hdr));
     else if (p.dtype == SWC_U16)
-        hipLaunchKernelGGL((unf_products<uint16_t, false>), dim3(nb), dim3(256), 0, s,
-                           (const uint16_t*)x, (const uint16_t*)y, E, plane, thr, hdr);
+        SWC_TRY(launch_kernel(&unf_products<uint16_t, false>, dim3(nb), dim3(256), 0, s,
+                           (const uint16_t*)x, (const uint16_t*)y, E, plane, thr, hdr));
     else
-        hipLaunchKernelGGL((unf_products<float, true>), dim3(nb), dim3(256), 0, s,
-                           (const float*)x, (const float*)y, E, plane, thr, hdr);
+        SWC_TRY(launch_kernel(&unf_products<float, true>, dim3(nb), dim3(256), 0, s,
+                           (const float*)x, (const float*)y, E, plane, thr, hdr));
     // step 2: one thread per row, moving sum along the row (E -> A)
-    hipLaunchKernelGGL(unf_moving_sum<kChUnf>, dim3(blocks_of(g.H, 64)), dim3(64), 0, s,
-                       (const double*)E, A, plane, g.H, (int64_t)g.W, g.W, (int64_t)1, g.kw, -g.ow);
+    SWC_TRY(launch_kernel(&unf_moving_sum<kChUnf>, dim3(blocks_of(g.H, 64)), dim3(64), 0, s,
+                       (const double*)E, A, plane, g.H, (int64_t)g.W, g.W, (int64_t)1, g.kw, -g.ow));
     // step 3: one thread per column, moving sum down the column (A -> E)
-    hipLaunchKernelGGL(unf_moving_sum<kChUnf>, dim3(blocks_of(g.W, 64)), dim3(64), 0, s,
-                       (const double*)A, E, plane, g.W, (int64_t)1, g.H, (int64_t)g.W, g.kh, -g.oh);
+    SWC_TRY(launch_kernel(&unf_moving_sum<kChUnf>, dim3(blocks_of(g.W, 64)), dim3(64), 0, s,
+                       (const double*)A, E, plane, g.W, (int64_t)1, g.H, (int64_t)g.W, g.kh, -g.oh));
     if (p.dtype == SWC_F32)
-        hipLaunchKernelGGL(unf_final<true>, dim3(nb), dim3(256), 0, s, (const double*)E, plane, g,
-                           (const float*)x, (const float*)y, (const uint32_t*)hdr, c, flags);
-    else
-        hipLaunchKernelGGL(unf_final<false>, dim3(nb), dim3(256), 0, s, (const double*)E, plane, g,
+        return launch_kernel(&unf_final<true>, dim3(nb), dim3(256), 0, s, (const double*)E, plane, g,
+                             (const float*)x, (const float*)y, (const uint32_t*)hdr, c, flags);
+    return launch_kernel(&unf_final<false>, dim3(nb), dim3(256), 0, s, (const double*)E, plane, g,
                            nullptr, nullptr, (const uint32_t*)hdr, c, flags);
-    return hipGetLastError();
 }
 
 }  // namespace swc

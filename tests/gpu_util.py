@@ -11,8 +11,15 @@ import oracle
 # f32 tolerance: |c_gpu - c64_oracle| <= 2^-24 (float32 output rounding is at
 # most 2^-25 for |c| <= 1; the FP64 sliding sums add far less on these inputs)
 F32_TOL = 2.0 ** -24
-# comparator modes: loose, only a sanity bound
+# comparator modes.  Naive float32 sums: a sanity bound only.  Compensated
+# float32 sums with the certification test: every certified window has both
+# computed variances above rho = 4096 times their rounding-error bound, so its
+# relative errors in N, Vx, Vy stay below 1/rho and |dc| <= 2/(rho - 1); the
+# output rounding adds 2^-24 (uncertified windows are recomputed two-pass).
 NAIVE_TOL = 0.5
+COMP_BOUND = 2.0 / 4095.0 + 2.0 ** -24
+# on the well-conditioned inputs of the parity tests the compensated sums
+# stay far inside that bound
 COMP_TOL = 1e-4
 
 

@@ -9,6 +9,7 @@
 import ctypes
 import os
 import re
+import sys
 import subprocess
 
 import numpy as np
@@ -225,3 +226,57 @@ def test_binding_rejects_host_tensors_before_any_launch(lib):
         swc.corr_into(p, x, x, out)
     with pytest.raises(ValueError, match="GPU"):
         swc.corr(x, x, (3, 3))
+
+
+_FAULT_SCRIPT = r"""
+import ctypes, sys
+sys.path.insert(0, sys.argv[1])
+import numpy as np
+import paper_1807_06507_amd as swc
+lib = swc._load()
+p = swc.make_problem((64, 80), "uint16", (7, 7), 1, "fill")
+fake = ctypes.c_void_p(4096)          # never dereferenced: nothing is launched
+st = lib.swc_corr(ctypes.byref(p), fake, fake, fake, None, None)
+st_ex = lib.swc_corr_ex(ctypes.byref(p), None, fake, fake, fake, None, None)
+ws = ctypes.c_uint64(0)
+assert lib.swc_scheme_workspace(ctypes.byref(p), 1, ctypes.byref(ws)) == 0
+st_sc = lib.swc_corr_scheme(ctypes.byref(p), 1, fake, fake, fake, None, fake, ws.value, None)
+st_cm = lib.swc_cloud_mask(fake, None, 100, ctypes.c_float(0.5), ctypes.c_float(-2.0), fake, None)
+try:
+    swc._check(st)
+    raised = None
+except swc.SwcError as e:
+    raised = (e.code, str(e))
+print(st, st_ex, st_sc, st_cm, raised)
+"""
+
+
+@pytest.mark.parametrize("inject", [True, False])
+def test_injected_launch_failure_reaches_python(lib, inject):
+    """SWC_FAULT_INJECT=launch: entry points that would launch return
+    SWC_ERR_LAUNCH before touching the device, and the binding turns the
+    status into SwcError.  Without the variable, a validation error (a fake
+    but invalid call) is still reported by validation first."""
+    env = dict(os.environ)
+    env.pop("SWC_FAULT_INJECT", None)
+    if inject:
+        env["SWC_FAULT_INJECT"] = "launch"
+        r = subprocess.run([sys.executable, "-c", _FAULT_SCRIPT, ROOT], env=env,
+                           capture_output=True, text=True, timeout=120)
+        assert r.returncode == 0, r.stderr
+        st, st_ex, st_sc, st_cm, rest = r.stdout.strip().split(" ", 4)
+        assert (int(st), int(st_ex), int(st_sc), int(st_cm)) == (10, 10, 10, 10), r.stdout
+        assert rest.startswith("(10, ") and "kernel launch failed" in rest, rest
+    else:
+        # the same calls with an invalid window fail validation before any
+        # launch, whether or not a failure is injected
+        bad = _FAULT_SCRIPT.replace("(7, 7), 1, \"fill\")", "(7, 7), 1, \"fill\"); p.window[0] = 0")
+        bad = bad.replace("assert lib.swc_scheme_workspace", "lib.swc_scheme_workspace")
+        for e in (None, "launch"):
+            if e:
+                env["SWC_FAULT_INJECT"] = e
+            r = subprocess.run([sys.executable, "-c", bad, ROOT], env=env, capture_output=True,
+                               text=True, timeout=120)
+            assert r.returncode == 0, r.stderr
+            st, st_ex, st_sc = r.stdout.strip().split(" ")[:3]
+            assert (int(st), int(st_ex), int(st_sc)) == (4, 4, 4), r.stdout

@@ -1,13 +1,18 @@
 """Precision sweep on the large-offset float32 pair (x ~ N(1000, 1), per-block
-rho): the running-sum formulation of Section 2 (Eqs. 1-4) evaluated three
-ways on the GPU and compared with the oracle's two-pass FP64 value.
+rho): the sliding-sum formulation (Section 1, steps 1-4, and its one-pass
+formula) evaluated four ways on the GPU and compared with the oracle's two-pass
+FP64 value (the Introduction's classical formula).
 
-  default  FP64 sliding sums with a certified fast path, two-pass rescan
-           otherwise: |dc| <= 2^-24 is asserted at every (k, s);
-  comp     compensated float32 sums: reported only (the float32 products
-           themselves already lose the variance on this input);
-  naive    plain float32 sums: reported only (cancellation leaves errors of
-           order 1 on this input).
+  default   FP64 sliding sums with a certified fast path, two-pass rescan
+            otherwise: |dc| <= 2^-24 is asserted at every (k, s);
+  comp      compensated float32 sums (TwoSum / TwoProd pairs) with a certified
+            fast path: a window passes only when its computed variances exceed
+            rho = 4096 times their rounding-error bound, so |dc| <= 2/(rho-1)
+            plus the float32 output rounding, asserted at every (k, s);
+  comp-raw  the same sums without the certification (debug bit 3): the
+            accuracy of the compensated sums themselves, reported;
+  naive     plain float32 sums: reported only (cancellation leaves errors of
+            order 1 on this input).
 
 Each (k, s) case compares sampled outputs of the full 4096x4096 map one by
 one against the oracle, so the whole sweep stays within a minute or two.
@@ -15,10 +20,11 @@ one against the oracle, so the whole sweep stays within a minute or two.
 import numpy as np
 import pytest
 
-from gpu_util import F32_TOL, gpu_corr, say
+from gpu_util import COMP_BOUND, F32_TOL, gpu_corr, say
 from workloads import precision_pair
 
 import oracle
+import paper_1807_06507_amd as swc
 
 pytestmark = pytest.mark.gpu
 
@@ -58,9 +64,18 @@ def test_precision_sweep(k):
         assert fmis == 0, f"k={k} s={s}: {fmis} flag mismatches"
         assert d_def <= F32_TOL, (k, s, d_def)
         cc, flc = gpu_corr(x, y, (k, k), s, "clip", accum="comp")
-        d_comp, _ = _maxdiff(cc, flc, o64, ofl, idx)
+        d_comp, fmis_c = _maxdiff(cc, flc, o64, ofl, idx)
+        assert fmis_c == 0, f"k={k} s={s}: comp {fmis_c} flag mismatches"
+        assert d_comp <= COMP_BOUND, (k, s, d_comp)
+        swc.set_debug(8)
+        try:
+            cr, flr = gpu_corr(x, y, (k, k), s, "clip", accum="comp")
+        finally:
+            swc.set_debug(0)
+        d_raw, _ = _maxdiff(cr, flr, o64, ofl, idx)
         cn, fln = gpu_corr(x, y, (k, k), s, "clip", accum="naive")
         d_naive, _ = _maxdiff(cn, fln, o64, ofl, idx)
-        rows.append((s, d_def, d_comp, d_naive))
-    for s, a, b, n in rows:
-        say(f"[precision] k={k:2d} s={s} default={a:.3e} comp={b:.3e} naive={n:.3e}")
+        rows.append((s, d_def, d_comp, d_raw, d_naive))
+    for s, a, b, r, n in rows:
+        say(f"[precision] k={k:2d} s={s} default={a:.3e} comp={b:.3e} comp-raw={r:.3e} "
+            f"naive={n:.3e}")
