@@ -133,11 +133,14 @@ def test_parity_wide_compiled_variants(dtype, R):
                                         ((150, 777), (2, 1), "valid", 32)]:
             x, y = _patched(shape, dtype, seed=k + R + shape[1])
             compare(x, y, (k, k), step, border, params=(R, th, 2), tag=f"wide k={k} R={R}")
-        # a rectangular window with the wide axis along the rows
+        # a rectangular window with the wide axis along the rows; several
+        # waves per workgroup (the generic kernel's LDS row buffers, which
+        # the launch parameters must also fit, allow 4 at R = 4 and 2 at R = 8)
+        wpb = 4 if R == 4 else 2
         x, y = _patched((160, 900), dtype, seed=5 * k + R)
-        compare(x, y, (5, k), 1, "clip", params=(R, 40, 4), tag=f"wide 5x{k} R={R}")
+        compare(x, y, (5, k), 1, "clip", params=(R, 40, wpb), tag=f"wide 5x{k} R={R}")
         if dtype == "f32":
-            _noflag_compare(x, y, (5, k), 1, "clip", params=(R, 40, 4), tag=f"5x{k} R={R}")
+            _noflag_compare(x, y, (5, k), 1, "clip", params=(R, 40, wpb), tag=f"5x{k} R={R}")
 
 
 @pytest.mark.parametrize("k", [3, 7, 15, 31])
