@@ -198,6 +198,22 @@ swc_status swc_scheme_workspace(const swc_problem *p, int32_t scheme, uint64_t *
 swc_status swc_corr_scheme(const swc_problem *p, int32_t scheme, const void *x, const void *y,
                            float *c, uint8_t *flags, void *workspace, uint64_t workspace_bytes,
                            void *stream);
+/* The schemes without a caller workspace, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops, hosts
+ * that forbid allocation): the workspace is a fixed array of
+ * SWC_SCHEME_SCRATCH_BYTES in device memory, one per device the library runs
+ * on, held until the process ends.  Same arguments, results and errors as
+ * swc_corr_scheme, except: returns SWC_ERR_WORKSPACE (before touching the
+ * device) when the problem needs more than SWC_SCHEME_SCRATCH_BYTES
+ * (UNFUSED: H * W <= 699,048; CUMSUM: H * W <= 1,677,721).  Calls no
+ * allocating routine.  All calls on one device share its array: calls that
+ * may overlap on one device (other streams, other threads) race and must be
+ * ordered by the caller.  The array keeps the last call's contents; each
+ * call initialises what it reads.  The first call on a device looks up the
+ * array's device address (no stream work). */
+#define SWC_SCHEME_SCRATCH_BYTES (64ull << 20)
+swc_status swc_corr_scheme_noalloc(const swc_problem *p, int32_t scheme, const void *x,
+                                   const void *y, float *c, uint8_t *flags, void *stream);
 /* ---- end-to-end runs from host memory ---------------------------------- */
 /* A plan for host-to-host runs of problem p (any ndim, step[0] == 1): the
  * input is cut into slabs of `band_rows` outputs along the first axis (plus

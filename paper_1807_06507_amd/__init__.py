@@ -115,6 +115,7 @@ def _load():
         lib.swc_batch_plan_destroy.restype = None
         lib.swc_scheme_workspace.argtypes = [P, ctypes.c_int32, ctypes.POINTER(ctypes.c_uint64)]
         lib.swc_corr_scheme.argtypes = [P, ctypes.c_int32, vp, vp, vp, vp, vp, ctypes.c_uint64, vp]
+        lib.swc_corr_scheme_noalloc.argtypes = [P, ctypes.c_int32, vp, vp, vp, vp, vp]
         lib.swc_host_plan_create.argtypes = [P, ctypes.c_int64, ctypes.c_int32, ctypes.POINTER(vp)]
         lib.swc_host_run.argtypes = [vp, vp, vp, vp, vp]
         lib.swc_host_plan_bands.argtypes = [vp]
@@ -349,6 +350,46 @@ def corr_scheme(x, y, window, scheme="unfused", border="fill", invalid=-2.0, mis
         ctypes.c_void_p(workspace.data_ptr()), ctypes.c_uint64(workspace.numel()), h)
     _check(code)
     return (out, fl) if return_flags else out
+
+
+# bytes of the fixed device workspace of corr_scheme_noalloc (64 MiB)
+SCHEME_SCRATCH_BYTES = 64 << 20
+
+
+def corr_scheme_noalloc(x, y, window, scheme="unfused", border="fill", invalid=-2.0,
+                        missing_le=-999.0, out=None, flags=None, stream=None):
+    """corr_scheme with the library's fixed device workspace instead of a
+    caller one (for callers that cannot allocate: pass ``out`` (and
+    ``flags``) to allocate nothing here either).  Problems needing more than
+    SCHEME_SCRATCH_BYTES raise; calls that overlap on one device race."""
+    import torch
+    _check_tensor(x, "x")
+    _check_tensor(y, "y")
+    if x.shape != y.shape or x.dtype != y.dtype:
+        raise ValueError("x and y must have the same shape and dtype")
+    if scheme not in SCHEMES:
+        raise ValueError(f"scheme must be one of {sorted(SCHEMES)}")
+    p = make_problem(tuple(x.shape), x.dtype, window, 1, border, "default", invalid, missing_le)
+    code = validate(p)
+    if code != 0:
+        raise ValueError(f"{STATUS.get(code)}: {status_str(code)}")
+    oshape = output_shape(p)
+    if out is None:
+        out = torch.empty(oshape, dtype=torch.float32, device=x.device)
+    _check_tensor(out, "out")
+    if tuple(out.shape) != tuple(oshape) or out.dtype != torch.float32:
+        raise ValueError(f"out must be float32 of shape {tuple(oshape)}")
+    if flags is not None:
+        _check_tensor(flags, "flags")
+        if tuple(flags.shape) != tuple(oshape) or flags.dtype != torch.uint8:
+            raise ValueError(f"flags must be uint8 of shape {tuple(oshape)}")
+    h = _stream_handle(stream, x.device)
+    code = _load().swc_corr_scheme_noalloc(
+        ctypes.byref(p), SCHEMES[scheme], ctypes.c_void_p(x.data_ptr()),
+        ctypes.c_void_p(y.data_ptr()), ctypes.c_void_p(out.data_ptr()),
+        ctypes.c_void_p(flags.data_ptr()) if flags is not None else None, h)
+    _check(code)
+    return out if flags is None else (out, flags)
 
 
 class HostPlan:

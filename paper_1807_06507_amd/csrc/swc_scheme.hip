@@ -17,6 +17,8 @@
 // integer inputs (FP64 integers below 2^53, certified float32 rounding); for
 // float inputs FP64 running sums with the rigorous certification test and the
 // two-pass fallback, using the global |x|, |y| maxima as the bound.
+#include <mutex>
+
 #include "swc_device.hpp"
 #include "swc_internal.h"
 
@@ -360,3 +362,63 @@ hipError_t launch_scheme(const swc_problem& p, int scheme, const void* x, const 
 }
 
 }  // namespace swc
+
+// ---- the schemes without a caller workspace ----------------------------
+// For callers that cannot allocate device memory (code under graph capture,
+// tight serving loops): the workspace is a fixed array in device memory.
+// Each device the library runs on holds its own copy until the process ends.
+// Every call on a device uses that device's copy, so calls that overlap on
+// one device (different streams, or threads) race; the array keeps the last
+// call's contents, and each scheme initialises what it reads (the unfused
+// scheme clears its header with a kernel; the cumulative sums overwrite
+// every word they read).
+static __device__ __align__(256) unsigned char scratch[SWC_SCHEME_SCRATCH_BYTES];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch[kMaxDevices] = {};
+
+// Device address of the current device's copy of `scratch`, looked up once
+// per device with that device current.  In host code the array's name is
+// only a stand-in: kernels and copies take this address.
+hipError_t scratch_address(void** out)
+{
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch[dev]) {
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        if (!p) return hipErrorInvalidSymbol;
+        g_scratch[dev] = p;
+    }
+    *out = g_scratch[dev];
+    return hipSuccess;
+}
+
+}  // namespace
+
+extern "C" swc_status swc_corr_scheme_noalloc(const swc_problem* p, int32_t scheme, const void* x,
+                                              const void* y, float* c, uint8_t* flags,
+                                              void* stream)
+{
+    swc_status st = swc_validate(p);
+    if (st != SWC_OK) return st;
+    if (!x || !y || !c) return SWC_ERR_NULL;
+    if (!swc::scheme_supported(*p, scheme)) return SWC_ERR_UNSUPPORTED;
+    if (swc::scheme_workspace_bytes(*p, scheme) > (uint64_t)SWC_SCHEME_SCRATCH_BYTES)
+        return SWC_ERR_WORKSPACE;
+    if (swc::fault_inject_launch()) return SWC_ERR_LAUNCH;
+    if (swc::sticky_error(hipPeekAtLastError())) return SWC_ERR_DEVICE;
+    void* ws = nullptr;
+    hipError_t e = scratch_address(&ws);
+    if (e != hipSuccess) return swc::sticky_error(e) ? SWC_ERR_DEVICE : SWC_ERR_LAUNCH;
+    e = swc::launch_scheme(*p, scheme, x, y, c, flags, ws, (hipStream_t)stream,
+                           swc_get_debug() & 1);
+    return swc::launch_status(e);
+}
