@@ -299,62 +299,172 @@ def window_step_sweep(torch, swc, sets, dtype, w, stream, reps=20):
     return res
 
 
-def run_batched(args, torch, swc, dev):
-    """The batched workload: persistent launches over all 64 pairs, against
-    64 per-image launches (eager and captured in one graph)."""
+def _sample_indices(oshape, n, seed):
+    """Output indices (C order) to check one by one: n uniform draws plus the
+    first and last output rows (border windows), unique and sorted."""
+    rng = np.random.default_rng(seed)
+    tot = int(np.prod(oshape))
+    rows = [np.arange(min(tot, oshape[-1]))] if len(oshape) > 1 else [np.arange(min(tot, 64))]
+    rows.append(np.arange(max(0, tot - (oshape[-1] if len(oshape) > 1 else 64)), tot))
+    return np.unique(np.concatenate([rng.integers(0, tot, n)] + rows)).astype(np.int64)
+
+
+def accuracy_single(torch, swc, x, y, w, p, c_timed, stream):
+    """Accuracy of the timed outputs against the FP64 oracle.  Integer input:
+    every output, bit for bit (the correctly rounded float32 of the exact
+    coefficient).  Float input: |c - c64| on sampled outputs, against the
+    2^-24 bound.  Flags come from one more launch with a flag map (the timed
+    launches write none); an invalid coefficient (-2) must sit exactly where
+    the oracle flags the window."""
+    import oracle
+    xd, yd = torch.from_numpy(x).to(c_timed.device), torch.from_numpy(y).to(c_timed.device)
+    fl = torch.empty(tuple(c_timed.shape), dtype=torch.uint8, device=c_timed.device)
+    c2 = torch.empty_like(c_timed)
+    swc.corr_into(p, xd, yd, c2, fl, None, stream)
+    torch.cuda.synchronize()
+    c = c_timed.cpu().numpy()
+    f = fl.cpu().numpy()
+    same_launch = bool(np.array_equal(c.view(np.uint32), c2.cpu().numpy().view(np.uint32)))
+    del xd, yd, c2
+    res = {"reference": "CPU FP64 oracle (two-pass formula, window by window)"}
+    t0 = time.perf_counter()
+    if x.dtype != np.float32 and c.size <= 40_000_000:
+        o32, _, ofl = oracle.corr(x, y, w["window"], w["step"], w["border"])
+        res.update({"outputs_checked": int(c.size), "sampled": False,
+                    "bit_exact": bool(np.array_equal(c.view(np.uint32), o32.view(np.uint32))),
+                    "c_mismatches": int(np.count_nonzero(c.view(np.uint32) != o32.view(np.uint32))),
+                    "flag_mismatches": int(np.count_nonzero(f != ofl))})
+    else:
+        idx = _sample_indices(c.shape, 20000, seed=17)
+        _, o64, ofl = oracle.corr(x, y, w["window"], w["step"], w["border"], indices=idx)
+        cs, fs = c.ravel()[idx], f.ravel()[idx]
+        ok = ofl == 0
+        d = float(np.max(np.abs(cs[ok].astype(np.float64) - o64[ok]))) if ok.any() else 0.0
+        res.update({"outputs_checked": int(idx.size), "sampled": True,
+                    "max_abs_dc": d, "bound": 2.0 ** -24, "within_bound": d <= 2.0 ** -24,
+                    "flag_mismatches": int(np.count_nonzero(fs != ofl)),
+                    "invalid_mismatches": int(np.count_nonzero((cs == np.float32(-2.0)) != ~ok))})
+    res["flag_launch_equals_timed"] = same_launch
+    res["oracle_s"] = round(time.perf_counter() - t0, 2)
+    return res
+
+
+def batched_comparison(torch, swc, dev, steps, warmup, with_cpu=False):
+    """The 64-pair batched workload: the persistent batch plan captured in
+    one HIP graph and replayed, against the same 64 pairs launched one by one
+    (eager, and captured in one graph), at the same accuracy: max |dc| against
+    the FP64 oracle on sampled outputs of both sides, and invalid-output
+    mismatches."""
+    import oracle
     from workloads import batched_pairs
     w = WORKLOADS["c3"]
+    t0 = time.perf_counter()
     pairs = batched_pairs(64, seed=1)
+    gen_s = time.perf_counter() - t0
     dp = [dict(x=torch.from_numpy(a).to(dev), y=torch.from_numpy(b).to(dev), window=k, step=1,
                border="clip") for a, b, k in pairs]
     px = sum(a.size for a, _, _ in pairs)
     algo_bytes = sum(a.nbytes + b.nbytes + a.size * 4 for a, b, _ in pairs)
-    plan = swc.BatchPlan(dp)
     stream = torch.cuda.current_stream(dev)
-    for _ in range(args.warmup):
+    plan = swc.BatchPlan(dp)
+    for _ in range(warmup):
         plan.launch()
-    elapsed, mean_ms = _timed_region(torch, stream, args.steps, lambda i: plan.launch())
+    _, eager_ms = _timed_region(torch, stream, steps, lambda i: plan.launch())
+    graph = plan.capture_graph()
+    for _ in range(max(3, warmup // 10)):
+        graph.replay()
+    elapsed, graph_ms = _timed_region(torch, stream, steps, lambda i: graph.replay())
+
     probs = [swc.make_problem(tuple(d["x"].shape), d["x"].dtype, d["window"], 1, "clip")
              for d in dp]
-
+    outs = [torch.empty_like(o) for o in plan.outputs]
     singles = [swc.prepare(pr, d["x"], d["y"], o, None, None, stream)
-               for pr, d, o in zip(probs, dp, plan.outputs)]
+               for pr, d, o in zip(probs, dp, outs)]
 
     def per_image(i):
         for f in singles:
             f()
-    per_image(0)
-    _, ms2 = _timed_region(torch, stream, max(3, args.steps // 4), per_image)
+    for _ in range(3):
+        per_image(0)
+    n_pi = max(3, steps // 4)
+    _, pi_ms = _timed_region(torch, stream, n_pi, per_image)
     g = torch.cuda.CUDAGraph()
     side = torch.cuda.Stream(device=dev)
     with torch.cuda.graph(g, stream=side):
-        for pr, d, o in zip(probs, dp, plan.outputs):
+        for pr, d, o in zip(probs, dp, outs):
             swc.corr_into(pr, d["x"], d["y"], o, None, None, torch.cuda.current_stream(dev))
     g.replay()
-    _, ms3 = _timed_region(torch, stream, max(3, args.steps // 4), lambda i: g.replay())
-    mean_s = mean_ms * 1e-3
-    line = {
-        "metric": METRIC, "value": round(args.steps * px / elapsed / 1e9, 3), "unit": "Gpixel/s",
-        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
-        "ms_per_step": round(elapsed / args.steps * 1e3, 5), "higher_is_better": True,
-        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
-        "config": {"workload": w["desc"], "pairs": 64, "pixels": px,
-                   "work_items": plan.items},
-        "roofline": {"bound": "hbm", "achieved": round(algo_bytes / mean_s / 1e9, 1),
+    _, pig_ms = _timed_region(torch, stream, n_pi, lambda i: g.replay())
+    torch.cuda.synchronize()
+
+    # accuracy of both sides' outputs (each holds the last timed run's result)
+    t1 = time.perf_counter()
+    dmax_b = dmax_p = 0.0
+    inv_b = inv_p = checked = 0
+    for i, ((a, b, k), ob, op) in enumerate(zip(pairs, plan.outputs, outs)):
+        idx = _sample_indices(tuple(ob.shape), 512, seed=100 + i)
+        _, o64, ofl = oracle.corr(a, b, (k, k), 1, "clip", indices=idx)
+        ok = ofl == 0
+        for arr, which in ((ob, "b"), (op, "p")):
+            cs = arr.cpu().numpy().ravel()[idx]
+            d = float(np.max(np.abs(cs[ok].astype(np.float64) - o64[ok]))) if ok.any() else 0.0
+            inv = int(np.count_nonzero((cs == np.float32(-2.0)) != ~ok))
+            if which == "b":
+                dmax_b, inv_b = max(dmax_b, d), inv_b + inv
+            else:
+                dmax_p, inv_p = max(dmax_p, d), inv_p + inv
+        checked += idx.size
+    acc_s = time.perf_counter() - t1
+    graph_s = graph_ms * 1e-3
+    res = {
+        "workload": w["desc"], "pairs": len(pairs), "pixels": px, "work_items": plan.items,
+        "batched_graph_ms": round(graph_ms, 5), "batched_eager_ms": round(eager_ms, 5),
+        "per_image_launches_ms": round(pi_ms, 5), "per_image_graph_ms": round(pig_ms, 5),
+        "speedup_vs_per_image": round(pi_ms / graph_ms, 3),
+        "speedup_vs_per_image_graph": round(pig_ms / graph_ms, 3),
+        "gpix_s": round(px / graph_s / 1e9, 2),
+        "roofline": {"bound": "hbm", "achieved": round(algo_bytes / graph_s / 1e9, 1),
                      "peak": HBM_PEAK_GBPS, "unit": "GB/s",
-                     "frac": round(algo_bytes / mean_s / 1e9 / HBM_PEAK_GBPS, 4),
+                     "frac": round(algo_bytes / graph_s / 1e9 / HBM_PEAK_GBPS, 4),
                      "traffic": _traffic_from_profiles(_kernel_source_hash("c3"), "c3")},
-        "kernel_ms_mean": round(mean_ms, 5),
-        "per_image_launches_ms": round(ms2, 5),
-        "per_image_graph_ms": round(ms3, 5),
-        "batched_vs_per_image": round(ms2 / mean_ms, 3),
+        "accuracy": {"outputs_checked_per_side": checked, "bound": 2.0 ** -24,
+                     "max_abs_dc_batched": dmax_b, "max_abs_dc_per_image": dmax_p,
+                     "invalid_mismatches_batched": inv_b, "invalid_mismatches_per_image": inv_p,
+                     "same_bound": dmax_b <= 2.0 ** -24 and dmax_p <= 2.0 ** -24},
         "algorithmic_bytes_per_launch": algo_bytes,
         "kernel_source_hash": _kernel_source_hash("c3"),
+        "host_s": {"generate": round(gen_s, 1), "oracle_samples": round(acc_s, 1)},
     }
-    if not args.no_cpu:
+    extra = {"elapsed": elapsed, "graph_ms": graph_ms, "algo_bytes": algo_bytes, "px": px}
+    if with_cpu:
         a, b, k = pairs[0]
-        line["cpu_baseline"] = cpu_baseline(a, b, dict(window=(k, k), step=(1, 1),
-                                                       border="clip"))
+        extra["cpu_baseline"] = cpu_baseline(a, b, dict(window=(k, k), step=(1, 1),
+                                                        border="clip"))
+    del graph, g, plan, dp, outs, singles
+    torch.cuda.synchronize()
+    return res, extra
+
+
+def run_batched(args, torch, swc, dev):
+    """The batched workload as the main line: the graph-replayed persistent
+    batch, with the per-image comparison and accuracy beside it."""
+    res, extra = batched_comparison(torch, swc, dev, args.steps, args.warmup,
+                                    with_cpu=not args.no_cpu)
+    line = {
+        "metric": METRIC, "value": round(args.steps * extra["px"] / extra["elapsed"] / 1e9, 3),
+        "unit": "Gpixel/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(extra["elapsed"] / args.steps * 1e3, 5), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": res["workload"], "pairs": res["pairs"], "pixels": res["pixels"],
+                   "work_items": res["work_items"], "launch": "hipGraph replay"},
+        "roofline": res["roofline"],
+        "kernel_ms_mean": res["batched_graph_ms"],
+        "batched": res,
+        "algorithmic_bytes_per_launch": extra["algo_bytes"],
+        "kernel_source_hash": res["kernel_source_hash"],
+    }
+    if "cpu_baseline" in extra:
+        line["cpu_baseline"] = extra["cpu_baseline"]
     return line
 
 
@@ -370,6 +480,8 @@ def main():
     ap.add_argument("--no-schemes", action="store_true",
                     help="skip the unfused baseline schemes and the host-pipeline run")
     ap.add_argument("--params", default="", help="R,TH,wpb[,minw,TY] launch parameters")
+    ap.add_argument("--no-batched", action="store_true",
+                    help="skip the batched-vs-per-image comparison in the default line")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -451,6 +563,14 @@ def main():
         "algorithmic_bytes_per_launch": algo_bytes,
         "kernel_source_hash": khash,
     }
+    line["accuracy"] = accuracy_single(torch, swc, x, y, w, p, sets[0][2], stream)
+    if not args.no_batched and args.config == "c1":
+        # the second half of the metric: batched vs per-image at the same
+        # accuracy, on the 64-pair workload
+        del launches
+        sets = sets[:1]
+        torch.cuda.empty_cache()
+        line["batched"], _ = batched_comparison(torch, swc, dev, max(10, args.steps // 4), 20)
     if not args.no_schemes and args.config == "c2":
         line["window_step_sweep"] = window_step_sweep(torch, swc, sets, x.dtype, w, stream)
     if not args.no_schemes and len(w["shape"]) == 2 and tuple(w["step"]) == (1, 1):
