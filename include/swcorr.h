@@ -126,7 +126,10 @@ typedef struct swc_problem {
  *                  2-D: 0 = as many rows as fill the GPU's resident
  *                  wavefront slots in one round
  *   waves_per_block: 1, 2 or 4 wavefronts per workgroup
- *   min_waves_per_eu: occupancy hint (0 = kernel default)
+ *   min_waves_per_eu: waves per SIMD to size the work for (0 = as many as
+ *                  fit): 2-D with tile_rows 0, the resident waves the
+ *                  default tile height fills; batched launches, the
+ *                  persistent waves per SIMD (0 = 2)
  *   tile_rows2:    3-D only: output rows per wavefront (2 or 4; 0 = 2)  */
 typedef struct swc_launch_params {
     int32_t cols_per_lane;

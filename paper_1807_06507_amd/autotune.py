@@ -1,6 +1,7 @@
 """Autotuner for the launch parameters of libswcorr.so.
 
-    python -m paper_1807_06507_amd.autotune [--quick] [--out PATH]
+    python -m paper_1807_06507_amd.autotune [--quick] [--only c1,c3] [--out PATH]
+                                            [--summary PATH]
 
 For each workload class (element type, dimensionality, window-size bucket,
 accumulation mode) it times candidate tile shapes on the GPU through the C ABI
@@ -8,10 +9,15 @@ accumulation mode) it times candidate tile shapes on the GPU through the C ABI
 that the library loads at initialisation (`tune_table.txt` next to
 libswcorr.so, or the file named by SWC_TUNE_TABLE).  Candidates:
   2-D:    cols_per_lane R in {4, 8}, tile rows TH (0 = one round of resident
-          waves), waves per workgroup
+          waves), waves per workgroup, and with TH = 0 the waves per SIMD
+          that round is sized for (min_waves_per_eu; 0 = as many as fit)
   1-D:    rows per wave TH, waves per workgroup (R fixed at 8)
   3-D:    planes per wave TH, output rows per wave TY, waves per workgroup
-  batch:  tile rows TH (0 = about four tiles per wave), waves per workgroup
+  batch:  tile rows TH (0 = about four tiles per wave), waves per workgroup,
+          persistent waves per SIMD (min_waves_per_eu; 0 = 2)
+With --only, the classes tuned replace their lines and every other line of
+the existing table is kept.  --summary writes every candidate's time (a
+markdown table) for the record.
 Timing uses HIP events on the launch stream over several launches whose
 input buffers rotate beyond the 256 MB Infinity Cache, as the benchmark does.
 
@@ -81,6 +87,9 @@ def _sets(x, y, oshape, per_set_bytes):
     return out
 
 
+_LOG = []   # (class label, candidate, microseconds) of every timed candidate
+
+
 def tune_single(x, y, window, step, border, candidates, label):
     import paper_1807_06507_amd as swc
     p = swc.make_problem(x.shape, x.dtype, window, step, border)
@@ -95,6 +104,7 @@ def tune_single(x, y, window, step, border, candidates, label):
         except Exception:
             continue
         print(f"  {label} {cand}: {t:.1f} us", flush=True)
+        _LOG.append((label, cand, t))
         if best is None or t < best[0]:
             best = (t, cand)
     del sets
@@ -115,6 +125,7 @@ def tune_batch(pairs, candidates, label):
         t = _time_launches(lambda i: plan.launch(), 1, reps=10, warm=2)
         plan.close()
         print(f"  {label} {cand}: {t:.1f} us", flush=True)
+        _LOG.append((label, cand, t))
         if best is None or t < best[0]:
             best = (t, cand)
     return best
@@ -125,6 +136,7 @@ def main():
     ap.add_argument("--quick", action="store_true", help="fewer candidates")
     ap.add_argument("--out", default=os.path.join(HERE, "tune_table.txt"))
     ap.add_argument("--only", default="", help="comma list: c0,c1,c2,c3,c4a,c4b")
+    ap.add_argument("--summary", default="", help="markdown file for every candidate's time")
     args = ap.parse_args()
     import torch
     import paper_1807_06507_amd as swc
@@ -134,15 +146,17 @@ def main():
     only = set(args.only.split(",")) if args.only else None
     ths = [0, 16, 24, 32] if not args.quick else [0, 24]
     wpbs = [1, 2, 4] if not args.quick else [2, 4]
-    cand2d = [(R, th, w) for R, th, w in itertools.product([4, 8], ths, wpbs)]
-    lines = []
+    minws = [0, 1, 2, 3] if not args.quick else [0, 2]
+    cand2d = [(R, th, w, mw) for R, th, w, mw in itertools.product([4, 8], ths, wpbs, minws)
+              if th == 0 or mw == 0]
+    lines = {}
 
     def emit(dt, nd, acc, kb, cand):
         line = (f"{DT_CODE[dt]} {nd} {acc} {kb} {cand[0]} {cand[1]} {cand[2]} "
                 f"{cand[3] if len(cand) > 3 else 0}")
         if len(cand) > 4:
             line += f" {cand[4]}"
-        lines.append(line)
+        lines[(DT_CODE[dt], nd, acc, kb)] = line
 
     t0 = time.time()
     if only is None or "c1" in only:
@@ -162,8 +176,8 @@ def main():
             emit("f32", 2, 0, kbucket(k), b[1])
     if only is None or "c3" in only:
         pairs = batched_pairs(64, seed=1)
-        candb = [(4, th, w) for th, w in itertools.product([0, 16, 24, 32, 40, 48, 64, 96, 128],
-                                                           [0, 1, 2])]
+        candb = [(4, th, w, mw) for th, w, mw in itertools.product(
+            [0, 16, 24, 32, 40, 48, 64, 96, 128], [0, 1, 2], [0, 1, 3, 4])]
         b = tune_batch(pairs, candb, "f32 batch")
         emit("f32", 2, 0, 0, b[1])
     if only is None or "c4b" in only:
@@ -177,12 +191,35 @@ def main():
                                                                       [2, 4])]
         b = tune_single(x, y, (7, 7, 7), 1, "clip", cand3, "f32 3-D k7")
         emit("f32", 3, 0, 7, b[1])
+    # merge: lines of classes not tuned in this run are kept as they were
+    kept = {}
+    if os.path.exists(args.out):
+        with open(args.out) as f:
+            for line in f:
+                fl = line.split()
+                if len(fl) >= 8 and not line.startswith("#"):
+                    kept[tuple(int(v) for v in fl[:4])] = line.strip()
+    kept.update(lines)
     with open(args.out, "w") as f:
-        f.write("# swcorr tuning table: dtype ndim accum kbucket R TH wpb min_waves\n")
-        f.write(f"# written by paper_1807_06507_amd.autotune on "
-                f"{torch.cuda.get_device_name(0)} in {time.time() - t0:.0f} s\n")
-        f.write("\n".join(lines) + "\n")
+        f.write("# swcorr tuning table: dtype ndim accum kbucket R TH wpb min_waves [TY]\n")
+        f.write(f"# written by paper_1807_06507_amd.autotune on {torch.cuda.get_device_name(0)}; "
+                f"last run: {','.join(sorted(only)) if only else 'all classes'} "
+                f"in {time.time() - t0:.0f} s\n")
+        f.write("\n".join(kept[k] for k in sorted(kept)) + "\n")
     print(open(args.out).read())
+    if args.summary:
+        with open(args.summary, "w") as f:
+            f.write("# Autotuner candidates (mean microseconds per launch)\n\n")
+            f.write(f"Command: `python -m paper_1807_06507_amd.autotune"
+                    f"{' --only ' + args.only if args.only else ''}"
+                    f"{' --quick' if args.quick else ''}` on {torch.cuda.get_device_name(0)}.\n\n")
+            f.write("| class | candidate (R, TH, wpb, min_waves[, TY]) | us | best |\n|---|---|---|---|\n")
+            best = {}
+            for lab, cand, t in _LOG:
+                if lab not in best or t < best[lab]:
+                    best[lab] = t
+            for lab, cand, t in _LOG:
+                f.write(f"| {lab} | {tuple(cand)} | {t:.1f} | {'*' if t == best[lab] else ''} |\n")
 
 
 if __name__ == "__main__":

@@ -157,15 +157,17 @@ swc_status swc_batch_plan_create(int32_t n, const swc_problem* p, const void* co
     }
     int TH = 0, wpb = 0, minw = 0;   // 0: chosen below
     swc_launch_params tuned;
-    if (!(lp && (lp->tile_rows || lp->waves_per_block)) &&
-        tune_lookup(p[0].dtype, 2, p[0].accum, 0, &tuned))
-        lp = &tuned;
-    if (lp && (lp->tile_rows || lp->waves_per_block)) {
+    auto given = [](const swc_launch_params* q) {
+        return q && (q->tile_rows || q->waves_per_block || q->min_waves_per_eu);
+    };
+    if (!given(lp) && tune_lookup(p[0].dtype, 2, p[0].accum, 0, &tuned)) lp = &tuned;
+    if (given(lp)) {
         if (lp->cols_per_lane && lp->cols_per_lane != kBatchR) return SWC_ERR_PARAM;
         TH = lp->tile_rows;
         wpb = lp->waves_per_block;
         minw = lp->min_waves_per_eu;
-        if (TH < 0 || TH > 4096 || !(wpb == 0 || wpb == 1 || wpb == 2 || wpb == 4))
+        if (TH < 0 || TH > 4096 || !(wpb == 0 || wpb == 1 || wpb == 2 || wpb == 4) ||
+            minw < 0 || minw > 8)
             return SWC_ERR_PARAM;
     }
     int dev = 0;

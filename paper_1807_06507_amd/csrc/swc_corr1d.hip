@@ -436,20 +436,13 @@ corr1d_kernel(P1D g)
             uint32_t fl;
             if constexpr (kFloat) {
                 const bool cert = (Vx > gx) & (Vy > gy);
-                const double rr = __builtin_amdgcn_rsq(q);
-                const double e = __builtin_fma(-(q * rr), rr, 1.0);
-                const double a0 = Nn * rr;
-                c = clamp_unit(__builtin_fma(0.5 * a0, e, a0));
+                c = clamp_unit(newton_ratio(Nn, q));
                 const bool miss = S.miss > 0;
                 bad = fb | miss;
                 pend = (!bad) & ((!cert) | ((g.force & 1) != 0));
                 fl = fb ? FL_BORDER : (miss ? FL_MISSING : 0u);
             } else {
-                const double rr = __builtin_amdgcn_rsq(q);
-                const double t = q * rr;
-                const double e = __builtin_fma(-t, rr, 1.0);
-                const double a0 = Nn * rr;
-                const double a = __builtin_fma(0.5 * a0, e, a0);
+                const double a = newton_ratio(Nn, q);
                 const uint32_t lo29 = (uint32_t)__double_as_longlong(a) & 0x1FFFFFFFu;
                 const bool amb = (lo29 - (0x10000000u - (1u << 15))) <= (2u << 15);
                 c = (float)a;

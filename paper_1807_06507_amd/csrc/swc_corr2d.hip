@@ -244,6 +244,7 @@ bool cfg_ok_2d(const swc_problem& p, const LaunchCfg& L)
     if (!(L.R == 1 || L.R == 2 || L.R == 4 || L.R == 8)) return false;
     if (!(L.wpb == 1 || L.wpb == 2 || L.wpb == 4)) return false;
     if (L.TH < 0 || L.TH > 4096) return false;   // 0: chosen per launch
+    if (L.minw < 0 || L.minw > 8) return false;
     if (wq_of(L.R, p.window[1], p.step[1]) < 1) return false;
     int mode = mode_of(p.dtype, p.accum);
     if (mode < 0) return false;
@@ -381,8 +382,10 @@ hipError_t launch_corr2d(const swc_problem& p, const int64_t* oshape, const Laun
         if (TH <= 0) {
             // one round of resident waves: as many tile rows as the free wave
             // slots allow across the tile columns, each as tall as that needs
-            const int64_t slots = (int64_t)device_cus() * wpb_f *
-                                  fast2d_blocks_per_cu(mode, L.R, g.kw, vec, wpb_f, smem_f);
+            // (min_waves_per_eu > 0: at most that many waves per SIMD)
+            int64_t per_cu = (int64_t)wpb_f * fast2d_blocks_per_cu(mode, L.R, g.kw, vec, wpb_f, smem_f);
+            if (L.minw > 0) per_cu = std::min<int64_t>(per_cu, 4 * (int64_t)L.minw);
+            const int64_t slots = (int64_t)device_cus() * std::max<int64_t>(1, per_cu);
             const int64_t ty = std::max<int64_t>(1, slots / std::max<int64_t>(1, tiles_x));
             TH = (int)std::min<int64_t>(4096, std::max<int64_t>(4, (g.OH + ty - 1) / ty));
         }

@@ -147,6 +147,29 @@ template <bool LEFT, int M> __device__ __forceinline__ Col<M> col_dpp(const Col<
     return r;
 }
 
+// a + (b of lane t-1) (LEFT) or a + (b of lane t+1), with 0 taken beyond the
+// wave's ends: one DPP-modified add.  The two wait states a DPP source needs
+// after its VALU write are inserted here (the compiler does not see inside).
+template <bool LEFT> __device__ __forceinline__ uint32_t add_shifted(uint32_t a, uint32_t b)
+{
+    uint32_t r;
+    if constexpr (LEFT)
+        asm("s_nop 1\n\tv_add_u32_dpp %0, %1, %2 wave_shr:1 row_mask:0xf bank_mask:0xf bound_ctrl:1"
+            : "=&v"(r) : "v"(b), "v"(a));
+    else
+        asm("s_nop 1\n\tv_add_u32_dpp %0, %1, %2 wave_shl:1 row_mask:0xf bank_mask:0xf bound_ctrl:1"
+            : "=&v"(r) : "v"(b), "v"(a));
+    return r;
+}
+template <bool LEFT> __device__ __forceinline__ int add_shifted(int a, int b)
+{
+    return (int)add_shifted<LEFT>((uint32_t)a, (uint32_t)b);
+}
+template <bool LEFT> __device__ __forceinline__ double add_shifted(double a, double b)
+{
+    return a + dpp_move<LEFT>(b);
+}
+
 template <int M> __device__ __forceinline__ void col_add(Col<M>& a, const Col<M>& b)
 {
     a.x += b.x; a.y += b.y; a.xx += b.xx; a.yy += b.yy;
@@ -158,6 +181,22 @@ template <int M> __device__ __forceinline__ void col_sub(Col<M>& a, const Col<M>
     a.x -= b.x; a.y -= b.y; a.xx -= b.xx; a.yy -= b.yy;
     if constexpr (M == MODE_F64) { a.xy -= b.xy; a.miss -= b.miss; }
     else a.xy2 -= b.xy2;
+}
+
+// a += b of the lane to the left (LEFT) or right, channel by channel (32-bit
+// integer channels as DPP-modified adds, FP64 channels moved, then added).
+template <bool LEFT, int M> __device__ __forceinline__ void col_add_shifted(Col<M>& a, const Col<M>& b)
+{
+    a.x = add_shifted<LEFT>(a.x, b.x);
+    a.y = add_shifted<LEFT>(a.y, b.y);
+    a.xx = add_shifted<LEFT>(a.xx, b.xx);
+    a.yy = add_shifted<LEFT>(a.yy, b.yy);
+    if constexpr (M == MODE_F64) {
+        a.xy = add_shifted<LEFT>(a.xy, b.xy);
+        a.miss = add_shifted<LEFT>(a.miss, b.miss);
+    } else {
+        a.xy2 = add_shifted<LEFT>(a.xy2, b.xy2);
+    }
 }
 
 // Running update with entering (x, y) and leaving (xo, yo) integer values.
@@ -301,22 +340,25 @@ __device__ __forceinline__ void hsum_onehop(const Col<M> (&V)[R], Emit&& emit)
     constexpr int RH = KW - 1 - LH;
     constexpr int JL = LH < R - 1 ? LH : R - 1;                   // last left-block output
     constexpr int JR = (R - 1 - RH) > (JL + 1) ? (R - 1 - RH) : (JL + 1);  // first right-block output
-    // sums of this lane's last m columns -> Lx[m] of the right neighbour
+    // sums of this lane's last m columns (the right neighbour's Lx[m]) and
+    // of its first m columns (the left neighbour's Rx[m]); each is shifted
+    // across the lanes where it is added
     Col<M> Lx[LH + 1];
-    Col<M> suf = V[R - 1];
+    Lx[1] = V[R - 1];
 #pragma unroll
-    for (int m = 1; m <= LH; m++) {
-        if (m > 1) col_add<M>(suf, V[R - m]);
-        Lx[m] = col_dpp<true, M>(suf);
+    for (int m = 2; m <= LH; m++) {
+        Lx[m] = Lx[m - 1];
+        col_add<M>(Lx[m], V[R - m]);
     }
-    // sums of this lane's first m columns -> Rx[m] of the left neighbour
+    const Col<M>& suf = Lx[LH];
     Col<M> Rx[RH + 1];
-    Col<M> pre = V[0];
+    Rx[1] = V[0];
 #pragma unroll
-    for (int m = 1; m <= RH; m++) {
-        if (m > 1 && m <= R) col_add<M>(pre, V[m - 1]);
-        Rx[m] = col_dpp<false, M>(pre);
+    for (int m = 2; m <= RH; m++) {
+        Rx[m] = Rx[m - 1];
+        if (m <= R) col_add<M>(Rx[m], V[m - 1]);
     }
+    const Col<M>& pre = Rx[RH];
     // left block: own columns 0..min(j+RH, R-1)
     Col<M> last;
     {
@@ -326,8 +368,8 @@ __device__ __forceinline__ void hsum_onehop(const Col<M> (&V)[R], Emit&& emit)
             const int b = j + RH;
             if (b <= R - 1) col_add<M>(P, V[b]);
             Col<M> S = P;
-            if (j < LH) col_add<M>(S, Lx[LH - j]);
-            if (b > R - 1) col_add<M>(S, Rx[b - R + 1]);
+            if (j < LH) col_add_shifted<true, M>(S, Lx[LH - j]);
+            if (b > R - 1) col_add_shifted<false, M>(S, Rx[b - R + 1]);
             emit(j, S);
             if (j == JL) last = S;
         }
@@ -348,7 +390,7 @@ __device__ __forceinline__ void hsum_onehop(const Col<M> (&V)[R], Emit&& emit)
             if (a < R - LH) col_add<M>(Q, V[a]);
             Col<M> S = Q;
             const int mr = j + RH - (R - 1);
-            if (mr > 0) col_add<M>(S, Rx[mr]);
+            if (mr > 0) col_add_shifted<false, M>(S, Rx[mr]);
             emit(j, S);
         }
     }
@@ -423,8 +465,9 @@ template <class T> __device__ __forceinline__ T opaque(T v)
 template <bool B> struct BoolTag {
     static constexpr bool value = B;
 };
-// Flag map chosen at run time (one code path for launches with and without).
-struct FlagsAtRuntime {};
+template <int V> struct IntTag {
+    static constexpr int value = V;
+};
 
 // Correctly rounded float32 of N / sqrt(q), q = Vx Vy, from exact integers
 // (q > 0): FP64 rsqrt estimate and one Newton step (relative error < 2^-38);
@@ -432,11 +475,7 @@ struct FlagsAtRuntime {};
 // rounding midpoint, where only the exact decision is trustworthy.
 __device__ __forceinline__ float rn32_fast(double N, double q, bool& amb)
 {
-    const double r = __builtin_amdgcn_rsq(q);
-    const double t = q * r;
-    const double e = __builtin_fma(-t, r, 1.0);        // 1 - q r^2
-    const double a0 = N * r;
-    const double a = __builtin_fma(0.5 * a0, e, a0);   // N r (1 + e/2)
+    const double a = newton_ratio(N, q);
     const uint32_t lo = (uint32_t)__double_as_longlong(a) & 0x1FFFFFFFu;
     amb = (lo - (0x10000000u - (1u << 15))) <= (2u << 15);
     return (float)a;
@@ -519,8 +558,8 @@ __device__ __forceinline__ void tile2d(const P2DF& g, const int tile, char* smem
     }
     // lane-aligned outputs (unit column step, centred windows, every lane
     // either full or empty): each lane stores its R results as vectors
-    const bool tile_vec = (g.vst & 1) &&
-                          __builtin_amdgcn_ballot_w64(omask != 0u && omask != kFull) == 0;
+    const bool lane_aligned = __builtin_amdgcn_ballot_w64(omask != 0u && omask != kFull) == 0;
+    const bool tile_vec = (g.vst & 1) && lane_aligned;
     const uint32_t voff = omask ? (uint32_t)c0 * 4u : kOffNone;    // c0 = first output column
     const uint32_t vfoff = omask ? (uint32_t)c0 : kOffNone;
 
@@ -582,27 +621,31 @@ __device__ __forceinline__ void tile2d(const P2DF& g, const int tile, char* smem
     };
 
     // ---- step 3-4 for output row p: window sums along the row, epilogue,
-    //      store.  IN: the row and every output column of the tile are
-    //      interior (full windows, no border handling). ----
+    //      store.  IN:
+    //        2: the output row's window rows and every output column of the
+    //           tile are interior (full windows, no border handling);
+    //        1: lane-aligned outputs (every lane's columns all outputs or
+    //           none) whose windows take their own clipped counts and
+    //           FILL-border bits: the tiles along the array's edges then
+    //           cost about as much as interior ones, so none of them holds
+    //           up the end of the launch;
+    //        0: the general case. ----
     auto out_row = [&](int p, auto in_tag, auto fl_tag, float (&cvals)[R],
                        uint32_t (&flw)[(R + 3) / 4]) {
-        constexpr bool IN = decltype(in_tag)::value;
-        // a flag map is written: fixed by the tag, or the launch's choice
-        constexpr bool FL_RT = std::is_same<decltype(fl_tag), FlagsAtRuntime>::value;
-        bool FL = false;
-        if constexpr (FL_RT) FL = has_flags;
-        else FL = decltype(fl_tag)::value;
+        constexpr int IN = decltype(in_tag)::value;
+        constexpr bool FL = decltype(fl_tag)::value;   // a flag map is written
         const int rlo_w = p * g.sh + g.oh, rhi_w = rlo_w + kh - 1;
         const bool row_b = fill && (rlo_w < 0 || rhi_w >= H);
         uint32_t fillb_r = 0, ncolp_r[(R + 3) / 4] = {};
-        if constexpr (!IN) {
+        if constexpr (IN != 2) {
             fillb_r = opaque(fillb);
 #pragma unroll
             for (int i = 0; i < (R + 3) / 4; i++) ncolp_r[i] = opaque(ncolp[i]);
         }
         auto ncol_r = [&](int j) -> int { return (int)((ncolp_r[j / 4] >> (8 * (j % 4))) & 0xFFu); };
         const int rl = max(rlo_w, 0), rh_ = min(rhi_w, H - 1);
-        const double nrow = (double)(rh_ - rl + 1);
+        const int nrow_i = rh_ - rl + 1;
+        const double nrow = (double)nrow_i;
         const double dn_in = (double)(kh * KW);
         double gx = 0.0, gy = 0.0;   // certification thresholds (float input)
         if constexpr (kFloat) {
@@ -613,16 +656,30 @@ __device__ __forceinline__ void tile2d(const P2DF& g, const int tile, char* smem
             gx = g.cert_g * Mx * Mx;
             gy = g.cert_g * My * My;
         }
-        bool any_pend = false;            // some output of this lane needs the rare path
+        // lanes with an output that needs the rare path: the compare results
+        // are combined as wave masks (scalar registers).  Interior rows of
+        // interior tiles skip the per-column output test (there a column that
+        // is not an output lies inside the array, so it is a well-formed
+        // window that rarely needs the rare path, which tests each output
+        // itself); lanes without any output are dropped once at the end.
+        uint64_t pend_w = 0;
         const bool force_exact = (g.force & 1) != 0;
+        const uint64_t fx_w = force_exact ? ~0ull : 0ull;
+        auto out_w = [&](int j) -> uint64_t {
+            if constexpr (IN >= 1) return ~0ull;   // lane-aligned: a lane's columns are all outputs or none
+            else return __builtin_amdgcn_ballot_w64(((omask >> j) & 1u) != 0u);
+        };
         // Window quantities of output j from its sums: N, Vx, Vy (exact
         // integers for integer input) and the FILL-border bit.
         auto nvv = [&](int j, const Col<M>& S, double& N, double& Vx, double& Vy, bool& fb)
             __attribute__((always_inline)) {
             double dn;
-            if constexpr (IN) {
+            if constexpr (IN == 2) {
                 dn = dn_in;
                 fb = false;
+            } else if constexpr (IN == 1) {
+                dn = (double)(nrow_i * ncol_r(j));
+                fb = row_b | (((fillb_r >> j) & 1u) != 0u);
             } else {
                 dn = nrow * (double)ncol_r(j);
                 fb = row_b || ((fillb_r >> j) & 1u);
@@ -644,16 +701,14 @@ __device__ __forceinline__ void tile2d(const P2DF& g, const int tile, char* smem
             nvv(j, S, N, Vx, Vy, fb);
             const double q = Vx * Vy;
             float cv;
-            bool bad, pend;
+            bool bad;
             if constexpr (kFloat) {
                 const bool cert = (Vx > gx) & (Vy > gy);
                 // FP64 rsqrt estimate and one Newton step
-                const double r = __builtin_amdgcn_rsq(q);
-                const double e = __builtin_fma(-(q * r), r, 1.0);
-                const double a0 = N * r;
-                cv = clamp_unit(__builtin_fma(0.5 * a0, e, a0));
+                cv = clamp_unit(newton_ratio(N, q));
                 bad = fb | (S.miss > 0);
-                pend = (!bad) & ((!cert) | force_exact);
+                pend_w |= (~__builtin_amdgcn_ballot_w64(cert) | fx_w) &
+                          ~__builtin_amdgcn_ballot_w64(bad) & out_w(j);
                 if (FL) {
                     const uint32_t fl = fb ? FL_BORDER : (S.miss > 0 ? FL_MISSING : 0);
                     flw[j / 4] |= fl << (8 * (j % 4));
@@ -663,7 +718,8 @@ __device__ __forceinline__ void tile2d(const P2DF& g, const int tile, char* smem
                 cv = rn32_fast(N, q, amb);
                 // Vx, Vy >= 0 are exact integers: a zero product is a zero variance
                 bad = fb | (q == 0.0);
-                pend = (!bad) & (amb | force_exact);
+                pend_w |= (__builtin_amdgcn_ballot_w64(amb) | fx_w) &
+                          ~__builtin_amdgcn_ballot_w64(bad) & out_w(j);
                 if (FL) {
                     const uint32_t fl = fb ? FL_BORDER
                                            : ((Vx == 0.0 ? FL_ZVAR_X : 0u) | (Vy == 0.0 ? FL_ZVAR_Y : 0u));
@@ -674,7 +730,6 @@ __device__ __forceinline__ void tile2d(const P2DF& g, const int tile, char* smem
             // instead of a branch around it for the rare invalid lanes)
             const float cvo = opaque(cv);
             cvals[j] = bad ? g.invalid : cvo;
-            any_pend = any_pend | (pend & (((omask >> j) & 1u) != 0));
             // epilogues are scheduled in groups of SWC_FAST2D_EPI_GROUP
             // outputs: interleaving more of them hides more latency but
             // costs registers
@@ -685,7 +740,7 @@ __device__ __forceinline__ void tile2d(const P2DF& g, const int tile, char* smem
         // (float input) for the outputs whose fast result is not certified.
         // The window sums are recomputed (the slide is deterministic), so the
         // common path keeps nothing for them.
-        if (__builtin_amdgcn_ballot_w64(any_pend)) {
+        if (pend_w & __builtin_amdgcn_ballot_w64(omask != 0u)) {
             hsum_row<M, R, KW>(V, [&](int j, const Col<M>& S) __attribute__((always_inline)) {
                 double N, Vx, Vy;
                 bool fb;
@@ -731,9 +786,7 @@ __device__ __forceinline__ void tile2d(const P2DF& g, const int tile, char* smem
     auto store_row = [&](bool emit, int64_t orow_p, auto svec_tag, auto fl_tag,
                          const float (&cvals)[R], const uint32_t (&flw)[(R + 3) / 4]) {
         constexpr bool SVEC = decltype(svec_tag)::value;
-        // run-time choice: flag stores go through a zero-length record when
-        // there is no map; compile-time choice: none are issued without one
-        constexpr bool RT = std::is_same<decltype(fl_tag), FlagsAtRuntime>::value;
+        constexpr bool FL = decltype(fl_tag)::value;   // flag stores (none without a map)
         const int64_t orow = emit ? orow_p : 0;
         const __amdgpu_buffer_rsrc_t rc =
             __builtin_amdgcn_make_buffer_rsrc(g.c + orow, (short)0, emit ? g.OW * 4 : 0, kBufWord3);
@@ -749,13 +802,9 @@ __device__ __forceinline__ void tile2d(const P2DF& g, const int tile, char* smem
             for (int j = 0; j < R; j++)
                 __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(cvals[j]), rc, qoff[j], 0, 0);
         }
-        bool fl_store = true;
-        if constexpr (!RT) fl_store = decltype(fl_tag)::value;
-        if (fl_store) {
-            const bool on = RT ? has_flags : true;
+        if constexpr (FL) {
             const __amdgpu_buffer_rsrc_t rf = __builtin_amdgcn_make_buffer_rsrc(
-                on ? (void*)(g.flags + orow) : (void*)g.c, (short)0, (emit && on) ? g.OW : 0,
-                kBufWord3);
+                (void*)(g.flags + orow), (short)0, emit ? g.OW : 0, kBufWord3);
             if constexpr (SVEC) {
 #pragma unroll
                 for (int i = 0; i < R / 4; i++)
@@ -808,7 +857,19 @@ __device__ __forceinline__ void tile2d(const P2DF& g, const int tile, char* smem
         int next_ready = kh - 1;
         int p = up ? p0 + ph - 1 : p0;
         const int pstep = up ? -1 : 1;
+        // Waves sharing a SIMD are issued oldest first, so with equal tiles
+        // the oldest would finish long before the others and leave its SIMD
+        // short of waves at the end.  Each wave instead lowers its priority
+        // as its march progresses (3 for the first quarter of the rows down
+        // to 0 for the last), so that waves behind catch up and the waves of
+        // a SIMD finish together.
+        const int q1 = nrows >> 2, q2 = nrows >> 1, q3 = nrows - q1;
+        __builtin_amdgcn_s_setprio(3);
         for (int base = -D; base < nrows; base += D) {
+            // (the first step of each D-row group at or past a quarter mark)
+            if ((unsigned)(q1 - base) < (unsigned)D) __builtin_amdgcn_s_setprio(2);
+            if ((unsigned)(q2 - base) < (unsigned)D) __builtin_amdgcn_s_setprio(1);
+            if ((unsigned)(q3 - base) < (unsigned)D) __builtin_amdgcn_s_setprio(0);
 #pragma unroll
             for (int u = 0; u < D; u++) {
                 const int li = base + u;
@@ -905,10 +966,13 @@ __device__ __forceinline__ void tile2d(const P2DF& g, const int tile, char* smem
                 if (emit) {
                     next_ready += g.sh;
                     const int rw = p * g.sh + g.oh;
-                    if (cols_inside && rw >= 0 && rw + kh - 1 <= H - 1)
-                        out_row(p, BoolTag<true>{}, fl_tag, cvals, flw);
+                    const bool row_in = rw >= 0 && rw + kh - 1 <= H - 1;
+                    if (row_in && cols_inside)
+                        out_row(p, IntTag<2>{}, fl_tag, cvals, flw);
+                    else if (lane_aligned)
+                        out_row(p, IntTag<1>{}, fl_tag, cvals, flw);
                     else
-                        out_row(p, BoolTag<false>{}, fl_tag, cvals, flw);
+                        out_row(p, IntTag<0>{}, fl_tag, cvals, flw);
                 }
                 store_row(emit, orow, svec_tag, fl_tag, cvals, flw);
                 if (emit) {
@@ -919,15 +983,9 @@ __device__ __forceinline__ void tile2d(const P2DF& g, const int tile, char* smem
         }
     };
     // whole-vector stores for the tile (every output lane full, flags
-    // either absent or aligned as well).  Float input: separate code for
-    // launches with and without a flag map (without, no flag is formed or
-    // stored); integer input keeps one path, which measured faster there.
-    if constexpr (!kFloat) {
-        if (tile_vec && (!has_flags || (g.vst & 2)))
-            march(BoolTag<true>{}, FlagsAtRuntime{});
-        else
-            march(BoolTag<false>{}, FlagsAtRuntime{});
-    } else if (has_flags) {
+    // either absent or aligned as well).  Separate code for launches with
+    // and without a flag map (without, no flag is formed or stored).
+    if (has_flags) {
         if (tile_vec && (g.vst & 2))
             march(BoolTag<true>{}, BoolTag<true>{});
         else

@@ -462,7 +462,7 @@ __device__ __forceinline__ void tile3d(const P3D& g, const int tile, char* smem)
                         const double Vy = __builtin_fma(dn, A3.yy, -(A3.y * A3.y));
                         const bool cert = (Vx > gx) && (Vy > gy) && !(g.force & 1);
                         if (cert) {
-                            cv = clamp_unit(N * rsqrt64(Vx * Vy));
+                            cv = clamp_unit(newton_ratio(N, Vx * Vy));
                         } else {
                             fl = twopass_window((const float*)g.x, (const float*)g.y, wb.s0, wb.s1,
                                                 wb.lo0, wb.hi0, wb.lo1, wb.hi1, wb.lo2, wb.hi2, &cv);
@@ -782,7 +782,7 @@ __device__ __forceinline__ void tile3d_cube(const P3D& g, const int tile, char* 
                         const double Vy = __builtin_fma(dn, A3.yy, -(A3.y * A3.y));
                         const bool cert = (Vx > gx) && (Vy > gy) && !(g.force & 1);
                         if (cert) {
-                            cv = clamp_unit(N * rsqrt64(Vx * Vy));
+                            cv = clamp_unit(newton_ratio(N, Vx * Vy));
                         } else {
                             const int64_t clo = (int64_t)qj[j] * g.sx + g.ox;
                             fl = twopass_window((const float*)g.x, (const float*)g.y,

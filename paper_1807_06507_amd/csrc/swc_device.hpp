@@ -326,20 +326,24 @@ __device__ __forceinline__ void u128_mul(uint64_t a, uint64_t b, uint64_t& lo, u
 }
 
 // r = (a1:a0) << s into 5 limbs; returns false when bits would be lost.
+// Limbs are placed by selects, never by a computed index, so the value stays
+// in registers.
 __device__ inline bool u320_from_shifted(uint64_t a0, uint64_t a1, int s, U320& r)
 {
-    for (int i = 0; i < 5; i++) r.w[i] = 0;
-    int limb = s >> 6, bit = s & 63;
-    uint64_t src[3] = {a0, a1, 0};
-    bool ok = true;
-    for (int i = 0; i < 3; i++) {
-        uint64_t v_lo = bit ? (src[i] << bit) : src[i];
-        uint64_t v_hi = bit ? (src[i] >> (64 - bit)) : 0;
-        int d = i + limb;
-        if (v_lo) { if (d < 5) r.w[d] |= v_lo; else ok = false; }
-        if (v_hi) { if (d + 1 < 5) r.w[d + 1] |= v_hi; else ok = false; }
-    }
-    return ok;
+    const int limb = s >> 6, bit = s & 63;
+    // (a1:a0) << bit as three limbs v0, v1, v2
+    const uint64_t v0 = a0 << bit;
+    const uint64_t v1 = bit ? ((a1 << bit) | (a0 >> (64 - bit))) : a1;
+    const uint64_t v2 = bit ? (a1 >> (64 - bit)) : 0;
+    r.w[0] = limb == 0 ? v0 : 0;
+    r.w[1] = limb == 0 ? v1 : (limb == 1 ? v0 : 0);
+    r.w[2] = limb == 0 ? v2 : (limb == 1 ? v1 : (limb == 2 ? v0 : 0));
+    r.w[3] = limb == 1 ? v2 : (limb == 2 ? v1 : (limb == 3 ? v0 : 0));
+    r.w[4] = limb == 2 ? v2 : (limb == 3 ? v1 : (limb == 4 ? v0 : 0));
+    // limbs that would land beyond the fifth
+    const bool lost = (limb == 3 && v2 != 0) || (limb == 4 && (v1 | v2) != 0) ||
+                      (limb >= 5 && (v0 | v1 | v2) != 0);
+    return !lost;
 }
 
 // r = m * (b1:b0), m < 2^64 -> 3 limbs (stored into 5)
@@ -441,6 +445,17 @@ __device__ __forceinline__ double rsqrt64(double q)
     return r;
 }
 
+// N / sqrt(q) for q > 0 from the hardware rsqrt estimate r (relative error
+// below 2^-20) and one Newton step: N r (1 + e/2) with e = 1 - q r^2.
+// Relative error below 2^-38.
+__device__ __forceinline__ double newton_ratio(double N, double q)
+{
+    const double r = __builtin_amdgcn_rsq(q);
+    const double e = __builtin_fma(-(q * r), r, 1.0);
+    const double a0 = N * r;
+    return __builtin_fma(0.5 * a0, e, a0);
+}
+
 __device__ __forceinline__ float clamp_unit(double c)
 {
     c = c > 1.0 ? 1.0 : c;
@@ -453,13 +468,15 @@ __device__ __forceinline__ float clamp_unit(double c)
 // for float windows that the error bound cannot certify.  The window is the
 // box [lo, hi] (inclusive, already clipped to the array) of a C-ordered
 // array with up to three dimensions: strides (s0, s1, 1).
-// Returns the flags (ZVAR bits) and writes c.
+// Returns the flags (ZVAR bits) in bits 32..39 and c's bits in bits 0..31
+// (a value rather than a pointer: the caller's result stays in registers and
+// the call needs no stack).
 // ---------------------------------------------------------------------------
-__device__ __noinline__ uint8_t twopass_window(const float* __restrict__ x,
-                                               const float* __restrict__ y, int64_t s0,
-                                               int64_t s1, int64_t lo0, int64_t hi0,
-                                               int64_t lo1, int64_t hi1, int64_t lo2,
-                                               int64_t hi2, float* cval)
+__device__ __noinline__ uint64_t twopass_window_packed(const float* __restrict__ x,
+                                                       const float* __restrict__ y, int64_t s0,
+                                                       int64_t s1, int64_t lo0, int64_t hi0,
+                                                       int64_t lo1, int64_t hi1, int64_t lo2,
+                                                       int64_t hi2)
 {
     double sx = 0.0, sy = 0.0;
     float x0 = x[lo0 * s0 + lo1 * s1 + lo2];
@@ -478,7 +495,7 @@ __device__ __noinline__ uint8_t twopass_window(const float* __restrict__ x,
                 n++;
             }
     uint8_t fl = (eqx ? FL_ZVAR_X : 0) | (eqy ? FL_ZVAR_Y : 0);
-    if (fl) return fl;
+    if (fl) return (uint64_t)fl << 32;
     double mx = sx / (double)n, my = sy / (double)n;
     double sxy = 0.0, sxx = 0.0, syy = 0.0;
     for (int64_t a = lo0; a <= hi0; a++)
@@ -490,8 +507,20 @@ __device__ __noinline__ uint8_t twopass_window(const float* __restrict__ x,
                 sxx += dx * dx;
                 syy += dy * dy;
             }
-    *cval = clamp_unit(sxy / __builtin_sqrt(sxx * syy));
-    return 0;
+    return (uint64_t)__float_as_uint(clamp_unit(sxy / __builtin_sqrt(sxx * syy)));
+}
+
+// The same with the coefficient written to *cval (inlined: *cval is the
+// caller's register) and the flags returned.
+__device__ __forceinline__ uint8_t twopass_window(const float* __restrict__ x,
+                                                  const float* __restrict__ y, int64_t s0,
+                                                  int64_t s1, int64_t lo0, int64_t hi0,
+                                                  int64_t lo1, int64_t hi1, int64_t lo2,
+                                                  int64_t hi2, float* cval)
+{
+    const uint64_t r = twopass_window_packed(x, y, s0, s1, lo0, hi0, lo1, hi1, lo2, hi2);
+    *cval = __uint_as_float((uint32_t)r);
+    return (uint8_t)(r >> 32);
 }
 
 // ---------------------------------------------------------------------------
