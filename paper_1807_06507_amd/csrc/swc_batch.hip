@@ -41,8 +41,8 @@ constexpr int kBatchR = 4;
 template <int M, int KW>
 __device__ __forceinline__ void batch_tile(const P2DF& g, int vec, int tile, char* lds)
 {
-    if (vec) tile2d<M, kBatchR, KW, true>(g, tile, lds);
-    else tile2d<M, kBatchR, KW, false>(g, tile, lds);
+    if (vec) tile2d<M, kBatchR, KW, true, false>(g, tile, lds);
+    else tile2d<M, kBatchR, KW, false, false>(g, tile, lds);
 }
 
 template <int M>
@@ -56,7 +56,17 @@ __attribute__((amdgpu_waves_per_eu(2, 8))) corr2d_batch_kernel(const BatchItem* 
     const int wpb = blockDim.x / kWave;
     const int64_t gid = (int64_t)xcd_remap(blockIdx.x, gridDim.x) * wpb + wv;
     char* lds = smem + (size_t)wv * lds_stride;
+    // Every wave takes the same share of the list.  Waves sharing a SIMD are
+    // issued oldest first; each wave lowers its priority as it moves through
+    // its share (3 for the first quarter down to 0 for the last), so that
+    // the waves of a SIMD keep pace and finish together.
+    const int64_t span = total - gid;
     for (int64_t it = gid; it < total; it += nwaves) {
+        const int64_t done4 = 4 * (it - gid);
+        if (done4 < span) __builtin_amdgcn_s_setprio(3);
+        else if (done4 < 2 * span) __builtin_amdgcn_s_setprio(2);
+        else if (done4 < 3 * span) __builtin_amdgcn_s_setprio(1);
+        else __builtin_amdgcn_s_setprio(0);
         // pair owning item `it` (wave-uniform)
         int lo = 0, hi = n - 1;
         while (lo < hi) {
@@ -175,21 +185,34 @@ swc_status swc_batch_plan_create(int32_t n, const swc_problem* p, const void* co
     int cus = 256;
     hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
 
+    // vector row loads for pair i (the tile code's VEC variant)
+    auto vec_of = [&](int i) {
+        const size_t esz = p[i].dtype == SWC_U8 ? 1 : (p[i].dtype == SWC_U16 ? 2 : 4);
+        const size_t va = esz * kBatchR;
+        if (esz == 4) return ((uintptr_t)x[i] % 4 == 0 && (uintptr_t)y[i] % 4 == 0) ? 1 : 0;
+        return ((uintptr_t)x[i] % va == 0 && (uintptr_t)y[i] % va == 0 &&
+                p[i].shape[1] % kBatchR == 0) ? 1 : 0;
+    };
+    // LDS bytes per wave of pair i's tiles: its row ring (none for wide windows)
+    auto lds_of = [&](int i) {
+        return (fast2d_lds_per_wave(mode, kBatchR, p[i].window[0], p[i].window[1],
+                                    vec_of(i) != 0) + 15) & ~15;
+    };
     // pairs the persistent kernel takes (the others run as separate launches)
     auto eligible = [&](int i) {
         return (mode == MODE_U8 || mode == MODE_U16 || mode == MODE_F64) &&
                batch_kw_ok(p[i].window[1]) && p[i].shape[0] < (1ll << 30) &&
                p[i].shape[1] < (1ll << 28) &&   // rows are raw buffers (< 2^31 bytes)
-               fast2d_lds_per_wave(mode, kBatchR, p[i].window[0]) <= 64 * 1024;
+               lds_of(i) <= 64 * 1024;
     };
-    // per pair: LDS ring bytes per wave, and the resident waves per CU that
-    // ring allows; pairs with the same cap share one persistent launch
+    // per pair: the resident waves per CU its LDS ring allows; pairs with the
+    // same cap share one persistent launch
     int lds_cu = 160 * 1024;
     hipDeviceGetAttribute(&lds_cu, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, dev);
-    auto lds_of = [&](int i) {
-        return (fast2d_lds_per_wave(mode, kBatchR, p[i].window[0]) + 15) & ~15;
+    auto cap_of = [&](int i) {
+        const int l = lds_of(i);
+        return l > 0 ? std::min(8, std::max(1, lds_cu / l)) : 8;
     };
-    auto cap_of = [&](int i) { return std::min(8, std::max(1, lds_cu / lds_of(i))); };
     int64_t tile_rows_total = 0;   // sum over pairs of output rows x tile columns
     for (int i = 0; i < n; i++) {
         if (!eligible(i)) continue;
@@ -216,13 +239,6 @@ swc_status swc_batch_plan_create(int32_t n, const swc_problem* p, const void* co
     // groups by occupancy cap (lowest first); inside a group widest windows
     // first (their tiles cost the most, so the tail of the persistent loop is
     // made of cheap tiles), then by alignment so concurrent waves share code
-    auto vec_of = [&](int i) {
-        const size_t esz = p[i].dtype == SWC_U8 ? 1 : (p[i].dtype == SWC_U16 ? 2 : 4);
-        const size_t va = esz * kBatchR;
-        if (esz == 4) return ((uintptr_t)x[i] % 4 == 0 && (uintptr_t)y[i] % 4 == 0) ? 1 : 0;
-        return ((uintptr_t)x[i] % va == 0 && (uintptr_t)y[i] % va == 0 &&
-                p[i].shape[1] % kBatchR == 0) ? 1 : 0;
-    };
     std::vector<int> cap(n, 8);
     for (int i = 0; i < n; i++)
         if (eligible(i)) cap[i] = cap_of(i);

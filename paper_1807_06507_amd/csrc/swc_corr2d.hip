@@ -345,10 +345,11 @@ hipError_t launch_corr2d(const swc_problem& p, const int64_t* oshape, const Laun
     const bool dims32 = g.H < ((int64_t)1 << 31) - 2 * kWave * 8 &&
                         g.W * 4 < ((int64_t)1 << 31) - 2 * kWave * 8 * 4;
     // waves per workgroup: as requested, halved while the LDS rings of the
-    // workgroup would exceed 64 KB
+    // workgroup would exceed 64 KB (wide windows keep no ring)
     int wpb_f = L.wpb;
-    while (wpb_f > 1 && (size_t)wpb_f * fast2d_lds_per_wave(mode, L.R, g.kh) > 64 * 1024) wpb_f /= 2;
-    const size_t smem_f = (size_t)wpb_f * fast2d_lds_per_wave(mode, L.R, g.kh);
+    const int lds_w = fast2d_lds_per_wave(mode, L.R, g.kh, g.kw, g.vec != 0);
+    while (wpb_f > 1 && (size_t)wpb_f * lds_w > 64 * 1024) wpb_f /= 2;
+    const size_t smem_f = (size_t)wpb_f * lds_w;
     if (!(force & 2) && dims32 && fast2d_supported(mode, L.R, g.kw) && smem_f <= 64 * 1024) {
         P2DF f;
         f.x = x;

@@ -51,16 +51,24 @@ __host__ __device__ inline bool fast2d_supported(int mode, int R, int KW)
 }
 
 // LDS bytes per wave: the raw-row ring (k_h rows).
-__host__ __device__ inline int fast2d_ring_bytes(int mode, int R, int kh)
+__host__ __device__ constexpr int fast2d_ring_bytes(int mode, int R, int kh)
 {
-    const int esz = mode == MODE_U8 ? 1 : (mode == MODE_U16 ? 2 : 4);
-    const int nw = (esz * R + 3) / 4;
-    const int miss = (mode == MODE_F64) ? 1 : 0;
-    return kh * kWave * 4 * (2 * nw + miss);
+    return kh * kWave * 4 *
+           (2 * (((mode == MODE_U8 ? 1 : (mode == MODE_U16 ? 2 : 4)) * R + 3) / 4) +
+            ((mode == MODE_F64) ? 1 : 0));
 }
-__host__ __device__ inline int fast2d_lds_per_wave(int mode, int R, int kh)
+// Wide windows: the tile code reads the row leaving the window a second time
+// (it is k_h rows behind the entering one, mostly an Infinity Cache hit)
+// instead of parking k_h rows in LDS, where a ring above 24 KB per wave
+// (taking k_h = k_w) would hold the resident waves per CU below six.  Vector
+// row loads only (the leaving row is read like the entering one).
+__host__ __device__ constexpr bool fast2d_reread(int mode, int R, int KW, bool vec)
 {
-    return (fast2d_ring_bytes(mode, R, kh) + 15) & ~15;
+    return vec && fast2d_ring_bytes(mode, R, KW) > 24 * 1024;
+}
+__host__ __device__ inline int fast2d_lds_per_wave(int mode, int R, int kh, int kw, bool vec)
+{
+    return fast2d_reread(mode, R, kw, vec) ? 0 : ((fast2d_ring_bytes(mode, R, kh) + 15) & ~15);
 }
 
 // Output columns per tile when outputs are lane-aligned (unit column step,
@@ -333,7 +341,7 @@ __host__ __device__ constexpr bool hsum_one_hop()
     return KW / 2 <= R && KW - 1 - KW / 2 <= R && KW >= 3;
 }
 
-template <int M, int R, int KW, class Emit>
+template <int M, int R, int KW, bool EARLY, class Emit>
 __device__ __forceinline__ void hsum_onehop(const Col<M> (&V)[R], Emit&& emit)
 {
     constexpr int LH = KW / 2;
@@ -359,6 +367,20 @@ __device__ __forceinline__ void hsum_onehop(const Col<M> (&V)[R], Emit&& emit)
         if (m <= R) col_add<M>(Rx[m], V[m - 1]);
     }
     const Col<M>& pre = Rx[RH];
+    // float input with windows up to 7 wide (EARLY): the partial sums are
+    // shifted across the lanes as soon as they are formed, so the moves of
+    // their FP64 channels overlap the adds that follow (measured faster
+    // there; wider windows would hold too many shifted sums at once);
+    // otherwise they are shifted where they are added, 32-bit channels as
+    // DPP-modified adds
+    constexpr bool kEarly = EARLY && (M == MODE_F64) && KW <= 7;
+    Col<M> LxS[kEarly ? LH + 1 : 1], RxS[kEarly ? RH + 1 : 1];
+    if constexpr (kEarly) {
+#pragma unroll
+        for (int m = 1; m <= LH; m++) LxS[m] = col_dpp<true, M>(Lx[m]);
+#pragma unroll
+        for (int m = 1; m <= RH; m++) RxS[m] = col_dpp<false, M>(Rx[m]);
+    }
     // left block: own columns 0..min(j+RH, R-1)
     Col<M> last;
     {
@@ -368,8 +390,13 @@ __device__ __forceinline__ void hsum_onehop(const Col<M> (&V)[R], Emit&& emit)
             const int b = j + RH;
             if (b <= R - 1) col_add<M>(P, V[b]);
             Col<M> S = P;
-            if (j < LH) col_add_shifted<true, M>(S, Lx[LH - j]);
-            if (b > R - 1) col_add_shifted<false, M>(S, Rx[b - R + 1]);
+            if constexpr (kEarly) {
+                if (j < LH) col_add<M>(S, LxS[LH - j]);
+                if (b > R - 1) col_add<M>(S, RxS[b - R + 1]);
+            } else {
+                if (j < LH) col_add_shifted<true, M>(S, Lx[LH - j]);
+                if (b > R - 1) col_add_shifted<false, M>(S, Rx[b - R + 1]);
+            }
             emit(j, S);
             if (j == JL) last = S;
         }
@@ -390,7 +417,84 @@ __device__ __forceinline__ void hsum_onehop(const Col<M> (&V)[R], Emit&& emit)
             if (a < R - LH) col_add<M>(Q, V[a]);
             Col<M> S = Q;
             const int mr = j + RH - (R - 1);
-            if (mr > 0) col_add_shifted<false, M>(S, Rx[mr]);
+            if (mr > 0) {
+                if constexpr (kEarly) col_add<M>(S, RxS[mr]);
+                else col_add_shifted<false, M>(S, Rx[mr]);
+            }
+            emit(j, S);
+        }
+    }
+}
+
+// One-hop window sums when no window reaches both neighbours (k_w/2 + 1 + k_w/2
+// <= R: the outputs near the lane's left edge read only the left neighbour,
+// those near its right edge only the right one): the left half of the
+// outputs is formed first with the left neighbour's suffix sums, then the
+// right half with the right neighbour's prefix sums, so only one side's
+// partial sums are held at a time (fewer registers at R = 8).
+template <int M, int R, int KW>
+__host__ __device__ constexpr bool hsum_two_phase()
+{
+    return KW / 2 + (KW - 1 - KW / 2) <= R - 1 && KW >= 3;
+}
+
+template <int M, int R, int KW, class Emit>
+__device__ __forceinline__ void hsum_twophase(const Col<M> (&V)[R], Emit&& emit)
+{
+    constexpr int LH = KW / 2;
+    constexpr int RH = KW - 1 - LH;
+    // output j reads columns j - LH .. j + RH: outputs j < LH reach into the
+    // left neighbour, outputs j > R - 1 - RH into the right one, and those
+    // in between lie inside the lane
+    {
+        Col<M> Lx[LH + 1];               // sums of the left neighbour's last m columns
+        Lx[1] = V[R - 1];
+#pragma unroll
+        for (int m = 2; m <= LH; m++) {
+            Lx[m] = Lx[m - 1];
+            col_add<M>(Lx[m], V[R - m]);
+        }
+        Col<M> P = V[0];                 // V[0 .. j + RH]
+#pragma unroll
+        for (int c = 1; c < RH; c++) col_add<M>(P, V[c]);
+#pragma unroll
+        for (int j = 0; j < LH; j++) {
+            col_add<M>(P, V[j + RH]);
+            Col<M> S = P;
+            col_add_shifted<true, M>(S, Lx[LH - j]);
+            emit(j, S);
+        }
+        // windows inside the lane: output LH reads columns 0 .. LH + RH
+        // (P holds 0 .. LH - 1 + RH), the next ones slide by one column
+        if constexpr (LH <= R - 1 - RH) {
+            Col<M> S = P;
+            col_add<M>(S, V[LH + RH]);
+            emit(LH, S);
+#pragma unroll
+            for (int j = LH + 1; j <= R - 1 - RH; j++) {
+                col_add<M>(S, V[j + RH]);
+                col_sub<M>(S, V[j - 1 - LH]);
+                emit(j, S);
+            }
+        }
+    }
+    __builtin_amdgcn_sched_barrier(0);
+    {
+        Col<M> Rx[RH + 1];               // sums of the right neighbour's first m columns
+        Rx[1] = V[0];
+#pragma unroll
+        for (int m = 2; m <= RH; m++) {
+            Rx[m] = Rx[m - 1];
+            col_add<M>(Rx[m], V[m - 1]);
+        }
+        Col<M> Q = V[R - 1];             // V[j - LH .. R - 1]
+#pragma unroll
+        for (int c = 2; c <= LH; c++) col_add<M>(Q, V[R - c]);
+#pragma unroll
+        for (int j = R - 1; j > R - 1 - RH; j--) {
+            col_add<M>(Q, V[j - LH]);
+            Col<M> S = Q;
+            col_add_shifted<false, M>(S, Rx[j + RH - (R - 1)]);
             emit(j, S);
         }
     }
@@ -420,12 +524,15 @@ template <int R, int KW> __device__ __forceinline__ float reach_max(float v)
     return fmaxf(ml, mr);
 }
 
-// Window sums of one output row, whichever form fits the window width.
-template <int M, int R, int KW, class Emit>
+// Window sums of one output row, whichever form fits the window width
+// (EARLY: see hsum_onehop).
+template <int M, int R, int KW, bool EARLY, class Emit>
 __device__ __forceinline__ void hsum_row(const Col<M> (&V)[R], Emit&& emit)
 {
-    if constexpr (hsum_one_hop<M, R, KW>())
-        hsum_onehop<M, R, KW>(V, emit);
+    if constexpr (hsum_two_phase<M, R, KW>())
+        hsum_twophase<M, R, KW>(V, emit);
+    else if constexpr (hsum_one_hop<M, R, KW>())
+        hsum_onehop<M, R, KW, EARLY>(V, emit);
     else
         hslide<M, R, KW>(V, emit);
 }
@@ -484,12 +591,17 @@ __device__ __forceinline__ float rn32_fast(double N, double q, bool& amb)
 // One tile of the fused 2-D correlation (see the file comment).  `smem` is
 // this wave's LDS region of fast2d_lds_per_wave(M, R, kh) bytes.  `tile` is
 // wave-uniform.
-template <int M, int R, int KW, bool VEC>
+// SINGLE: a launch of its own, one tile per wave.  A persistent caller
+// (SINGLE false) sets the waves' priorities itself, and the float exchange
+// shifts its sums where they are added, which needs fewer registers (its
+// kernel holds the code of every window width in one register allocation).
+template <int M, int R, int KW, bool VEC, bool SINGLE = true>
 __device__ __forceinline__ void tile2d(const P2DF& g, const int tile, char* smem)
 {
     using T = typename Tr<M>::T;
     constexpr int LH = KW / 2;
-    constexpr int D = fast2d_depth<M, R>();
+    // (one row ahead when the leaving row is read too: two loads per row in flight)
+    constexpr int D = fast2d_reread(M, R, KW, VEC) ? 1 : fast2d_depth<M, R>();
     constexpr int NW = Run<T, R>::NW;
     constexpr bool kFloat = (M == MODE_F64);
     constexpr uint32_t kFull = (1u << R) - 1u;
@@ -571,16 +683,19 @@ __device__ __forceinline__ void tile2d(const P2DF& g, const int tile, char* smem
     auto ring_at = [&](int slot, int i) __attribute__((always_inline)) {
         return kWordMajor ? (slot * NW + i) * kWave + lane : (slot * kWave + lane) * NW + i;
     };
+    constexpr bool kReread = fast2d_reread(M, R, KW, VEC);
     uint32_t* ringx = (uint32_t*)smem;
     uint32_t* ringy = ringx + kh * kWave * NW;
     int* ringm = (int*)(ringy + kh * kWave * NW);                // [kh][64] (float input)
-    for (int s = 0; s < kh; s++) {
+    if constexpr (!kReread) {
+        for (int s = 0; s < kh; s++) {
 #pragma unroll
-        for (int i = 0; i < NW; i++) {
-            ringx[ring_at(s, i)] = 0u;
-            ringy[ring_at(s, i)] = 0u;
+            for (int i = 0; i < NW; i++) {
+                ringx[ring_at(s, i)] = 0u;
+                ringy[ring_at(s, i)] = 0u;
+            }
+            if constexpr (kFloat) ringm[s * kWave + lane] = 0;
         }
-        if constexpr (kFloat) ringm[s * kWave + lane] = 0;
     }
 
     Col<M> V[R];
@@ -695,7 +810,7 @@ __device__ __forceinline__ void tile2d(const P2DF& g, const int tile, char* smem
                 Vy = __builtin_fma(dn, (double)S.yy, -(sy * sy));
             }
         };
-        hsum_row<M, R, KW>(V, [&](int j, const Col<M>& S) __attribute__((always_inline)) {
+        hsum_row<M, R, KW, SINGLE>(V, [&](int j, const Col<M>& S) __attribute__((always_inline)) {
             double N, Vx, Vy;
             bool fb;
             nvv(j, S, N, Vx, Vy, fb);
@@ -707,8 +822,10 @@ __device__ __forceinline__ void tile2d(const P2DF& g, const int tile, char* smem
                 // FP64 rsqrt estimate and one Newton step
                 cv = clamp_unit(newton_ratio(N, q));
                 bad = fb | (S.miss > 0);
-                pend_w |= (~__builtin_amdgcn_ballot_w64(cert) | fx_w) &
-                          ~__builtin_amdgcn_ballot_w64(bad) & out_w(j);
+                // (one ballot of the per-lane test: measured faster than
+                // combining the masks for float input)
+                const bool pnd = (!bad) & ((!cert) | force_exact) & (((omask >> j) & 1u) != 0);
+                pend_w |= __builtin_amdgcn_ballot_w64(pnd);
                 if (FL) {
                     const uint32_t fl = fb ? FL_BORDER : (S.miss > 0 ? FL_MISSING : 0);
                     flw[j / 4] |= fl << (8 * (j % 4));
@@ -741,7 +858,7 @@ __device__ __forceinline__ void tile2d(const P2DF& g, const int tile, char* smem
         // The window sums are recomputed (the slide is deterministic), so the
         // common path keeps nothing for them.
         if (pend_w & __builtin_amdgcn_ballot_w64(omask != 0u)) {
-            hsum_row<M, R, KW>(V, [&](int j, const Col<M>& S) __attribute__((always_inline)) {
+            hsum_row<M, R, KW, SINGLE>(V, [&](int j, const Col<M>& S) __attribute__((always_inline)) {
                 double N, Vx, Vy;
                 bool fb;
                 nvv(j, S, N, Vx, Vy, fb);
@@ -827,13 +944,17 @@ __device__ __forceinline__ void tile2d(const P2DF& g, const int tile, char* smem
     // ---- the march down the tile ----
     auto march = [&](auto svec_tag, auto fl_tag) {
         Run<T, R> pf[D];
+        Run<T, R> pfo[kReread ? D : 1];     // leaving rows (second read)
         // rows are issued in order, one per step: keep the next row's index
         // and byte offset in scalar registers instead of recomputing them
         const int64_t rowbytes = (int64_t)W * (int64_t)sizeof(T);
         int r_next = up ? i1 : i0;
         int64_t off_next = (int64_t)r_next * rowbytes;
         const int64_t off_step = up ? -rowbytes : rowbytes;
-        auto issue_next = [&](Run<T, R>& out) {
+        // march index of the next row issued: the row leaving the window
+        // with it is k_h rows behind, or none during the first k_h rows
+        int li_next = 0;
+        auto issue_next = [&](Run<T, R>& out, Run<T, R>& outo) {
             if constexpr (VEC) {
                 const bool rin = (unsigned)r_next < (unsigned)H;
                 const int nrec = rin ? (int)rowbytes : 0;
@@ -844,11 +965,24 @@ __device__ __forceinline__ void tile2d(const P2DF& g, const int tile, char* smem
                     __builtin_amdgcn_make_buffer_rsrc((void*)(Yb + o), (short)0, nrec, kBufWord3);
                 buf_load_words<NW>(bx, lane_vo, out.x);
                 buf_load_words<NW>(by, lane_vo, out.y);
+                if constexpr (kReread) {
+                    const int ro = up ? r_next + kh : r_next - kh;
+                    const bool oin = li_next >= kh && (unsigned)ro < (unsigned)H;
+                    const int nreco = oin ? (int)rowbytes : 0;
+                    const int64_t oo = oin ? off_next - (int64_t)kh * off_step : 0;
+                    const __amdgpu_buffer_rsrc_t bxo =
+                        __builtin_amdgcn_make_buffer_rsrc((void*)(Xb + oo), (short)0, nreco, kBufWord3);
+                    const __amdgpu_buffer_rsrc_t byo =
+                        __builtin_amdgcn_make_buffer_rsrc((void*)(Yb + oo), (short)0, nreco, kBufWord3);
+                    buf_load_words<NW>(bxo, lane_vo, outo.x);
+                    buf_load_words<NW>(byo, lane_vo, outo.y);
+                }
             } else {
                 issue(r_next, out);
             }
             r_next += up ? -1 : 1;
             off_next += off_step;
+            li_next++;
         };
         // output rows are emitted in order: element offset of row p
         int64_t orow = (int64_t)(up ? p0 + ph - 1 : p0) * (int64_t)g.OW;
@@ -862,14 +996,16 @@ __device__ __forceinline__ void tile2d(const P2DF& g, const int tile, char* smem
         // short of waves at the end.  Each wave instead lowers its priority
         // as its march progresses (3 for the first quarter of the rows down
         // to 0 for the last), so that waves behind catch up and the waves of
-        // a SIMD finish together.
+        // a SIMD finish together.  (A persistent caller sets priorities itself.)
         const int q1 = nrows >> 2, q2 = nrows >> 1, q3 = nrows - q1;
-        __builtin_amdgcn_s_setprio(3);
+        if constexpr (SINGLE) __builtin_amdgcn_s_setprio(3);
         for (int base = -D; base < nrows; base += D) {
             // (the first step of each D-row group at or past a quarter mark)
-            if ((unsigned)(q1 - base) < (unsigned)D) __builtin_amdgcn_s_setprio(2);
-            if ((unsigned)(q2 - base) < (unsigned)D) __builtin_amdgcn_s_setprio(1);
-            if ((unsigned)(q3 - base) < (unsigned)D) __builtin_amdgcn_s_setprio(0);
+            if constexpr (SINGLE) {
+                if ((unsigned)(q1 - base) < (unsigned)D) __builtin_amdgcn_s_setprio(2);
+                if ((unsigned)(q2 - base) < (unsigned)D) __builtin_amdgcn_s_setprio(1);
+                if ((unsigned)(q3 - base) < (unsigned)D) __builtin_amdgcn_s_setprio(0);
+            }
 #pragma unroll
             for (int u = 0; u < D; u++) {
                 const int li = base + u;
@@ -896,12 +1032,18 @@ __device__ __forceinline__ void tile2d(const P2DF& g, const int tile, char* smem
                     __builtin_memcpy(wx, vx, sizeof(T) * R);
                     __builtin_memcpy(wy, vy, sizeof(T) * R);
                 }
-                // ---- leaving row from the ring (zeros for the first k_h rows) ----
+                // ---- leaving row from the ring (zeros for the first k_h rows),
+                //      or from its second read ----
                 uint32_t ox[NW], oy[NW];
 #pragma unroll
                 for (int i = 0; i < NW; i++) {
-                    ox[i] = ringx[ring_at(slot, i)];
-                    oy[i] = ringy[ring_at(slot, i)];
+                    if constexpr (kReread) {
+                        ox[i] = pfo[u].x[i];
+                        oy[i] = pfo[u].y[i];
+                    } else {
+                        ox[i] = ringx[ring_at(slot, i)];
+                        oy[i] = ringy[ring_at(slot, i)];
+                    }
                 }
                 int omiss = 0, nmiss = 0;
                 T ax[R], ay[R], bx[R], by[R];
@@ -910,10 +1052,27 @@ __device__ __forceinline__ void tile2d(const P2DF& g, const int tile, char* smem
                 __builtin_memcpy(bx, ox, sizeof(T) * R);
                 __builtin_memcpy(by, oy, sizeof(T) * R);
                 if constexpr (kFloat) {
-                    omiss = ringm[slot * kWave + lane];
                     // positions outside the array read zero and are never
                     // missing, whatever the threshold
                     const bool row_in = (unsigned)row < (unsigned)H;
+                    if constexpr (kReread) {
+                        // the leaving row's missing positions, found again
+                        // (rows outside the array, and the first k_h rows of
+                        // the march, read zero and are never missing)
+                        const int rowo = up ? row + kh : row - kh;
+                        const bool rowo_in = li >= kh && (unsigned)rowo < (unsigned)H;
+#pragma unroll
+                        for (int j = 0; j < R; j++) {
+                            const bool inb = rowo_in && ((colok >> j) & 1u);
+                            const bool m = inb && (is_missing(bx[j], g.miss_thr) ||
+                                                   is_missing(by[j], g.miss_thr));
+                            bx[j] = m ? 0.f : bx[j];
+                            by[j] = m ? 0.f : by[j];
+                            omiss |= m ? (1 << j) : 0;
+                        }
+                    } else {
+                        omiss = ringm[slot * kWave + lane];
+                    }
 #pragma unroll
                     for (int j = 0; j < R; j++) {
                         const bool inb = row_in && ((colok >> j) & 1u);
@@ -927,15 +1086,17 @@ __device__ __forceinline__ void tile2d(const P2DF& g, const int tile, char* smem
                     }
                     __builtin_memcpy(wx, ax, sizeof(T) * R);
                     __builtin_memcpy(wy, ay, sizeof(T) * R);
-                    ringm[slot * kWave + lane] = nmiss;
+                    if constexpr (!kReread) ringm[slot * kWave + lane] = nmiss;
                 }
-                // same lane, same address: the read above returns the old row
+                if constexpr (!kReread) {
+                    // same lane, same address: the read above returns the old row
 #pragma unroll
-                for (int i = 0; i < NW; i++) {
-                    ringx[ring_at(slot, i)] = wx[i];
-                    ringy[ring_at(slot, i)] = wy[i];
+                    for (int i = 0; i < NW; i++) {
+                        ringx[ring_at(slot, i)] = wx[i];
+                        ringy[ring_at(slot, i)] = wy[i];
+                    }
+                    slot = (slot + 1 == kh) ? 0 : slot + 1;
                 }
-                slot = (slot + 1 == kh) ? 0 : slot + 1;
                 // ---- step 2: running column sums ----
 #pragma unroll
                 for (int j = 0; j < R; j++) {
@@ -955,7 +1116,7 @@ __device__ __forceinline__ void tile2d(const P2DF& g, const int tile, char* smem
                 }
                 // refill this prefetch slot only now: its registers are free, and
                 // the rows in the other slots stay in flight
-                issue_next(pf[u]);
+                issue_next(pf[u], pfo[kReread ? u : 0]);
                 const bool emit = li >= 0 && li == next_ready;
                 float cvals[R];
                 uint32_t flw[(R + 3) / 4];
@@ -1024,7 +1185,7 @@ __attribute__((amdgpu_waves_per_eu(fast2d_min_waves<M, R>(), 8))) corr2d_fast_ke
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
     const int tile = xcd_remap(blockIdx.x, gridDim.x) * wpb + wv;
     if (tile >= g.n_tiles) return;
-    tile2d<M, R, KW, VEC>(g, tile, smem + (size_t)wv * fast2d_lds_per_wave(M, R, g.kh));
+    tile2d<M, R, KW, VEC>(g, tile, smem + (size_t)wv * fast2d_lds_per_wave(M, R, g.kh, KW, VEC));
 }
 
 }  // namespace swc

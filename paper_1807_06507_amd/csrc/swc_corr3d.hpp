@@ -409,7 +409,7 @@ __device__ __forceinline__ void tile3d(const P3D& g, const int tile, char* smem)
 #pragma unroll
         for (int t = 0; t < TY; t++) {
             if (t >= pyn) continue;
-            hsum_row<M, R, KW>(VY[t], [&](int j, const Col<M>& S) __attribute__((always_inline)) {
+            hsum_row<M, R, KW, false>(VY[t], [&](int j, const Col<M>& S) __attribute__((always_inline)) {
                 slot(t, j).add(lane, S);
             });
         }
