@@ -16,7 +16,9 @@ mean launch duration, the time between two HIP events recorded on the launch
 stream around the K back-to-back launches of the timed region, over K), and
 cpu_baseline (the CPU oracle timed on the host cores on a bounded sample of
 the same workload).  A shorter pass with an event pair around every launch
-reports the spread of single launches.
+reports the spread of single launches.  Before the W warm-up steps, the
+hot path runs untimed for a quarter of a second (`settle` in the line), so
+the timed launches see the clocks of a loaded GPU even when W is small.
 """
 from __future__ import annotations
 
@@ -174,6 +176,24 @@ def copy_ceiling(torch, nbytes=1 << 30, reps=20):
     ms = s.elapsed_time(e) / reps
     del a, b
     return 2.0 * nbytes / (ms * 1e-3) / 1e9
+
+
+SETTLE_S = 0.25
+
+
+def _settle(torch, fn, seconds=SETTLE_S):
+    """Keep the GPU busy with fn(i) for about `seconds` of wall time (chunks
+    of 32 calls, synchronised) so that the timed launches run at the clocks
+    of a loaded GPU whatever the number of warm-up steps; returns the number
+    of calls.  None of these calls is timed or counted as a warm-up step."""
+    t0 = time.perf_counter()
+    n = 0
+    while time.perf_counter() - t0 < seconds:
+        for _ in range(32):
+            fn(n)
+            n += 1
+        torch.cuda.synchronize()
+    return n
 
 
 def _timed_region(torch, stream, n, fn):
@@ -367,6 +387,7 @@ def batched_comparison(torch, swc, dev, steps, warmup, with_cpu=False):
     algo_bytes = sum(a.nbytes + b.nbytes + a.size * 4 for a, b, _ in pairs)
     stream = torch.cuda.current_stream(dev)
     plan = swc.BatchPlan(dp)
+    settled = _settle(torch, lambda i: plan.launch())
     for _ in range(warmup):
         plan.launch()
     _, eager_ms = _timed_region(torch, stream, steps, lambda i: plan.launch())
@@ -434,6 +455,7 @@ def batched_comparison(torch, swc, dev, steps, warmup, with_cpu=False):
         "algorithmic_bytes_per_launch": algo_bytes,
         "kernel_source_hash": _kernel_source_hash("c3"),
         "host_s": {"generate": round(gen_s, 1), "oracle_samples": round(acc_s, 1)},
+        "settle": {"seconds": SETTLE_S, "launches": settled},
     }
     extra = {"elapsed": elapsed, "graph_ms": graph_ms, "algo_bytes": algo_bytes, "px": px}
     if with_cpu:
@@ -462,6 +484,7 @@ def run_batched(args, torch, swc, dev):
         "batched": res,
         "algorithmic_bytes_per_launch": extra["algo_bytes"],
         "kernel_source_hash": res["kernel_source_hash"],
+        "settle": res["settle"],
     }
     if "cpu_baseline" in extra:
         line["cpu_baseline"] = extra["cpu_baseline"]
@@ -529,6 +552,7 @@ def main():
     def step(i):
         launches[i % n_sets]()
 
+    settled = _settle(torch, step)
     for i in range(args.warmup):
         step(i)
     # the timed region: K launches back to back between one event pair (the
@@ -562,6 +586,7 @@ def main():
                               "min_ms": round(float(launch_ms.min()), 5)},
         "algorithmic_bytes_per_launch": algo_bytes,
         "kernel_source_hash": khash,
+        "settle": {"seconds": SETTLE_S, "launches": settled},
     }
     line["accuracy"] = accuracy_single(torch, swc, x, y, w, p, sets[0][2], stream)
     if not args.no_batched and args.config == "c1":

@@ -16,8 +16,8 @@ libswcorr.so, or the file named by SWC_TUNE_TABLE).  Candidates:
   batch:  tile rows TH (0 = about four tiles per wave), waves per workgroup,
           persistent waves per SIMD (min_waves_per_eu; 0 = 2)
 With --only, the classes tuned replace their lines and every other line of
-the existing table is kept.  --summary writes every candidate's time (a
-markdown table) for the record.
+the existing table is kept.  --summary writes, per class, the fastest
+candidates and the slowest one with their times (a markdown table).
 Timing uses HIP events on the launch stream over several launches whose
 input buffers rotate beyond the 256 MB Infinity Cache, as the benchmark does.
 
@@ -88,6 +88,7 @@ def _sets(x, y, oshape, per_set_bytes):
 
 
 _LOG = []   # (class label, candidate, microseconds) of every timed candidate
+SUMMARY_TOP = 6
 
 
 def tune_single(x, y, window, step, border, candidates, label):
@@ -212,15 +213,20 @@ def main():
             f.write("# Autotuner candidates (mean microseconds per launch)\n\n")
             f.write(f"Command: `python -m paper_1807_06507_amd.autotune"
                     f"{' --only ' + args.only if args.only else ''}"
-                    f"{' --quick' if args.quick else ''}` on {torch.cuda.get_device_name(0)}.\n\n")
-            f.write("| class | candidate (R, TH, wpb, min_waves[, TY]) | us | best |\n|---|---|---|---|\n")
-            best = {}
+                    f"{' --quick' if args.quick else ''}` on {torch.cuda.get_device_name(0)}"
+                    f" ({time.time() - t0:.0f} s).  Per class: the {SUMMARY_TOP} fastest "
+                    f"candidates, then the slowest; the first row is the table's entry.\n\n")
+            f.write("| class | candidate (R, TH, wpb, min_waves[, TY]) | us | of |\n"
+                    "|---|---|---|---|\n")
+            by = {}
             for lab, cand, t in _LOG:
-                if lab not in best or t < best[lab]:
-                    best[lab] = t
-            for lab, cand, t in _LOG:
-                f.write(f"| {lab} | {tuple(cand)} | {t:.1f} | {'*' if t == best[lab] else ''} |\n")
-
+                by.setdefault(lab, []).append((t, tuple(cand)))
+            for lab, rows in by.items():
+                rows.sort()
+                keep = rows[:SUMMARY_TOP] + (rows[-1:] if len(rows) > SUMMARY_TOP else [])
+                for i, (t, cand) in enumerate(keep):
+                    rank = f"{i + 1}" if i < SUMMARY_TOP else f"{len(rows)} (slowest)"
+                    f.write(f"| {lab} | {cand} | {t:.1f} | {rank}/{len(rows)} |\n")
 
 if __name__ == "__main__":
     main()

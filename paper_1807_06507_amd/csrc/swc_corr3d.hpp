@@ -595,9 +595,21 @@ __device__ __forceinline__ void tile3d_cube(const P3D& g, const int tile, char* 
     float hmx = 0.f, hmy = 0.f;
     bool dirty = false;          // wave-uniform: a missing value has entered this tile
 
+    // rows of the first (or only) row pair: the most any lane has
+    const int pyn_w = HALF ? min(TY, g.OH - ty * (2 * TY)) : pyn;
     int next_ready = g.kz - 1;
     int pz = pz0;
-    for (int li = 0; li < nz; li++) {
+    // One z step.  DIRTY = false: no missing value has entered the tile, so
+    // the entering rows are only screened and no missing counts are carried;
+    // a step whose screen finds one returns false before it has changed any
+    // state but the value maxima, and is taken again with DIRTY = true.  The
+    // DIRTY step first reads its rows once for the missing counts alone
+    // (window sums of the entering-minus-leaving indicators, added to the
+    // running counts), then once more for the masked values, so that neither
+    // pass holds more registers than the clean step.
+    auto zstep = [&](const int li, auto dirty_c) __attribute__((always_inline)) -> bool {
+        constexpr bool DIRTY = decltype(dirty_c)::value;
+        bool found = false;
         const int zin = zs + li;
         const int zout = li >= g.kz ? zin - g.kz : -1;
         const __amdgpu_buffer_rsrc_t rxi = prs(Xb, zin), ryi = prs(Yb, zin);
@@ -610,6 +622,51 @@ __device__ __forceinline__ void tile3d_cube(const P3D& g, const int tile, char* 
             buf_load_words<NW>(rxo, voff[r], o.xo);
             buf_load_words<NW>(ryo, voff[r], o.yo);
         };
+        if constexpr (kFloat && DIRTY) {
+            int V0m[R], MIDm[R];
+#pragma unroll
+            for (int r = 0; r < NYR; r++) {
+                uint32_t wxi[NW], wyi[NW], wxo[NW], wyo[NW];
+                buf_load_words<NW>(rxi, voff[r], wxi);
+                buf_load_words<NW>(ryi, voff[r], wyi);
+                buf_load_words<NW>(rxo, voff[r], wxo);
+                buf_load_words<NW>(ryo, voff[r], wyo);
+                T ax[R], ay[R], bx[R], by[R];
+                __builtin_memcpy(ax, wxi, sizeof(T) * R);
+                __builtin_memcpy(ay, wyi, sizeof(T) * R);
+                __builtin_memcpy(bx, wxo, sizeof(T) * R);
+                __builtin_memcpy(by, wyo, sizeof(T) * R);
+                // positions outside the volume read zero and are never missing
+                const bool row_in = (unsigned)(ys + r) < (unsigned)H && c0 >= 0 && c0 < W;
+                const bool in_i = row_in && (unsigned)zin < (unsigned)D;
+                const bool in_o = row_in && (unsigned)zout < (unsigned)D;
+#pragma unroll
+                for (int j = 0; j < R; j++) {
+                    const int dm = ((in_i && (is_missing(ax[j], g.miss_thr) |
+                                              is_missing(ay[j], g.miss_thr))) ? 1 : 0) -
+                                   ((in_o && (is_missing(bx[j], g.miss_thr) |
+                                              is_missing(by[j], g.miss_thr))) ? 1 : 0);
+                    if (r == 0) {
+                        V0m[j] = dm;
+                    } else if (r == 1) {
+                        MIDm[j] = dm;
+                    } else if (r < KW) {
+                        MIDm[j] += dm;
+                    } else {
+                        V0m[j] += MIDm[j];
+                        MIDm[j] += dm;
+                    }
+                }
+            }
+#pragma unroll
+            for (int t = 0; t < TY; t++) {
+                if (t >= pyn_w) continue;
+                int o[R];
+                hsum_scalar<int, R, KW>(t == 0 ? V0m : MIDm, o);
+#pragma unroll
+                for (int j = 0; j < R; j++) s3miss[t][j] += o[j];
+            }
+        }
         Col<M> V0[R], MID[R];    // MID becomes output row 1's sums after the last row
         issue(0);
         issue(1);
@@ -625,48 +682,47 @@ __device__ __forceinline__ void tile3d_cube(const P3D& g, const int tile, char* 
             int m[R], mo[R];
 #pragma unroll
             for (int j = 0; j < R; j++) { m[j] = 0; mo[j] = 0; }
-            if constexpr (kFloat) {
-                if (!dirty) {
-                    // entering values: finite and above the threshold?
-                    bool ok = true;
-                    float mxr = 0.f, myr = 0.f;
+            if constexpr (kFloat && !DIRTY) {
+                // entering values: finite and above the threshold?  (the
+                // leaving plane entered earlier and passed this test then)
+                bool ok = true;
+                float mxr = 0.f, myr = 0.f;
 #pragma unroll
-                    for (int j = 0; j < R; j++) {
-                        ok = ok & (ax[j] > g.miss_thr) & (ay[j] > g.miss_thr);
-                        mxr = fmaxf(mxr, __builtin_fabsf(ax[j]));
-                        myr = fmaxf(myr, __builtin_fabsf(ay[j]));
-                    }
-                    ok = ok & (mxr < __builtin_inff()) & (myr < __builtin_inff());
-                    if (__builtin_amdgcn_ballot_w64(!ok)) {
-                        dirty = true;             // the per-element path below bounds |x|
-                    } else {
-                        hmx = fmaxf(hmx, mxr);
-                        hmy = fmaxf(hmy, myr);
-                    }
+                for (int j = 0; j < R; j++) {
+                    ok = ok & (ax[j] > g.miss_thr) & (ay[j] > g.miss_thr);
+                    mxr = fmaxf(mxr, __builtin_fabsf(ax[j]));
+                    myr = fmaxf(myr, __builtin_fabsf(ay[j]));
                 }
-                if (dirty) {
-                    // positions outside the volume read zero and are never missing
-                    const bool row_in = (unsigned)(ys + r) < (unsigned)H && c0 >= 0 && c0 < W;
-                    const bool in_i = row_in && (unsigned)zin < (unsigned)D;
-                    const bool in_o = row_in && (unsigned)zout < (unsigned)D;
+                ok = ok & (mxr < __builtin_inff()) & (myr < __builtin_inff());
+                if (__builtin_amdgcn_ballot_w64(!ok)) {
+                    found = true;                 // the step is taken again, masked
+                } else {
+                    hmx = fmaxf(hmx, mxr);
+                    hmy = fmaxf(hmy, myr);
+                }
+            }
+            if constexpr (kFloat && DIRTY) {
+                // positions outside the volume read zero and are never missing
+                const bool row_in = (unsigned)(ys + r) < (unsigned)H && c0 >= 0 && c0 < W;
+                const bool in_i = row_in && (unsigned)zin < (unsigned)D;
+                const bool in_o = row_in && (unsigned)zout < (unsigned)D;
 #pragma unroll
-                    for (int j = 0; j < R; j++) {
-                        m[j] = (in_i && (is_missing(ax[j], g.miss_thr) |
-                                         is_missing(ay[j], g.miss_thr))) ? 1 : 0;
-                        mo[j] = (in_o && (is_missing(bx[j], g.miss_thr) |
-                                          is_missing(by[j], g.miss_thr))) ? 1 : 0;
-                        ax[j] = m[j] ? 0.f : ax[j];
-                        ay[j] = m[j] ? 0.f : ay[j];
-                        bx[j] = mo[j] ? 0.f : bx[j];
-                        by[j] = mo[j] ? 0.f : by[j];
-                        hmx = fmaxf(hmx, __builtin_fabsf(ax[j]));
-                        hmy = fmaxf(hmy, __builtin_fabsf(ay[j]));
-                    }
+                for (int j = 0; j < R; j++) {
+                    m[j] = (in_i && (is_missing(ax[j], g.miss_thr) |
+                                     is_missing(ay[j], g.miss_thr))) ? 1 : 0;
+                    mo[j] = (in_o && (is_missing(bx[j], g.miss_thr) |
+                                      is_missing(by[j], g.miss_thr))) ? 1 : 0;
+                    ax[j] = m[j] ? 0.f : ax[j];
+                    ay[j] = m[j] ? 0.f : ay[j];
+                    bx[j] = mo[j] ? 0.f : bx[j];
+                    by[j] = mo[j] ? 0.f : by[j];
+                    hmx = fmaxf(hmx, __builtin_fabsf(ax[j]));
+                    hmy = fmaxf(hmy, __builtin_fabsf(ay[j]));
                 }
             }
 #pragma unroll
             for (int j = 0; j < R; j++) {
-                const Col<M> d = col_delta<M, T>(ax[j], ay[j], bx[j], by[j], m[j], mo[j]);
+                const Col<M> d = col_delta<M, T>(ax[j], ay[j], bx[j], by[j], 0, 0);
                 if (r == 0) {
                     V0[j] = d;
                 } else if (r == 1) {
@@ -681,6 +737,9 @@ __device__ __forceinline__ void tile3d_cube(const P3D& g, const int tile, char* 
             __builtin_amdgcn_sched_barrier(0);
         }
 
+        if constexpr (!DIRTY) {
+            if (found) return false;             // nothing of this step was kept
+        }
         // ---- x-window sums, running 3-D sums, and (plane finished) the epilogue ----
         const bool ready = li == next_ready;
         if (ready) next_ready += g.sz;
@@ -699,8 +758,6 @@ __device__ __forceinline__ void tile3d_cube(const P3D& g, const int tile, char* 
                 gy = g.cert_g * (double)my * (double)my;
             }
         }
-        // rows of the first (or only) row pair: the most any lane has
-        const int pyn_w = HALF ? min(TY, g.OH - ty * (2 * TY)) : pyn;
 #pragma unroll
         for (int t = 0; t < TY; t++) {
             if (t >= pyn_w) continue;
@@ -748,9 +805,6 @@ __device__ __forceinline__ void tile3d_cube(const P3D& g, const int tile, char* 
             chan(std::integral_constant<int, 2>{});
             chan(std::integral_constant<int, 3>{});
             chan(std::integral_constant<int, 4>{});
-            if constexpr (col_nfields<M>() == 6) {
-                if (dirty) chan(std::integral_constant<int, 5>{});
-            }
             if (!ready) continue;
             const int ylo = (py0 + t) + g.oy, yhi = ylo + KW - 1;
             const bool rowb = fill && (ylo < 0 || yhi >= H);
@@ -774,7 +828,7 @@ __device__ __forceinline__ void tile3d_cube(const P3D& g, const int tile, char* 
                 if (fb) {
                     fl = FL_BORDER;
                 } else if constexpr (kFloat) {
-                    if (A3.miss > 0) {
+                    if (DIRTY && A3.miss > 0) {
                         fl = FL_MISSING;
                     } else {
                         const double N = __builtin_fma(dn, A3.xy, -(A3.x * A3.y));
@@ -806,6 +860,18 @@ __device__ __forceinline__ void tile3d_cube(const P3D& g, const int tile, char* 
             }
         }
         if (ready) ++pz;
+        return true;
+    };
+    for (int li = 0; li < nz; li++) {
+        if constexpr (kFloat) {
+            if (!dirty) {
+                if (zstep(li, std::false_type{})) continue;
+                dirty = true;
+            }
+            zstep(li, std::true_type{});
+        } else {
+            zstep(li, std::false_type{});
+        }
     }
 }
 

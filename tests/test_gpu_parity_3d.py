@@ -108,3 +108,24 @@ def test_parity_3d_missing_enters_mid_march():
     for border in ("clip", "fill"):
         compare(x, y, (7, 7, 7), 1, border, tag="3d-missing-late", params=(4, 40, 1, 0, 2))
         compare(x, y, (5, 5, 5), 1, border, tag="3d-missing-late")
+
+
+def test_parity_3d_missing_dense_square():
+    """About one value in fifty missing, from the first plane on, on the
+    specialised step (rows a multiple of 4 long) for every compiled window
+    width, whole-wave and half-wave tiles: the steps that carry missing
+    counts against the oracle, output by output."""
+    x, y = random_pair((20, 18, 128), "f32", seed=21, kind="lognormal")
+    rng = np.random.default_rng(5)
+    x[rng.random(x.shape) < 0.02] = -1000.0
+    y[rng.random(y.shape) < 0.01] = np.nan
+    for k in (3, 5, 7, 9):
+        for border in ("clip", "fill"):
+            compare(x, y, (k, k, k), 1, border, tag="3d-missing-dense")
+    compare(x, y, (7, 7, 7), 1, "clip", tag="3d-missing-dense", params=(4, 8, 1, 0, 2))
+    # 256-wide rows take the half-wave tiles (three halves instead of two waves)
+    x, y = random_pair((12, 10, 256), "f32", seed=22, kind="lognormal")
+    x[rng.random(x.shape) < 0.02] = -1000.0
+    y[rng.random(y.shape) < 0.01] = np.inf
+    for k in (5, 7):
+        compare(x, y, (k, k, k), 1, "clip", tag="3d-missing-dense-halves")
