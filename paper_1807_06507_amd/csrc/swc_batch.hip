@@ -320,10 +320,8 @@ swc_status swc_batch_plan_create(int32_t n, const swc_problem* p, const void* co
         g.tiles_y = (int)((osh[0] + TH - 1) / TH);
         g.n_tiles = tiles_x * g.tiles_y;
         const double th_ext = (double)(TH - 1) * q.step[0] + q.window[0];
-        // same chain as the single-pair launch of this tile code
-        const double chain = 2.0 * th_ext + 2.0 * q.window[1] + 2.0 * kBatchR + 2.0;
-        g.cert_g = cert_factor(mode, (double)q.window[0] * q.window[1], chain,
-                               (double)(q.window[0] + 1) * (q.window[1] + 1));
+        // the same bound as the single-pair launch of this tile code
+        g.cert_g = fast2d_cert(mode, kBatchR, q.window[0], q.window[1], th_ext);
         b.tile0 = tile0;
         b.kw = q.window[1];
         b.vec = vec_of(i);

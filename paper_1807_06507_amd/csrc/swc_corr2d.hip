@@ -395,12 +395,9 @@ hipError_t launch_corr2d(const swc_problem& p, const int64_t* oshape, const Laun
         const int64_t ntf = tiles_x * f.tiles_y;
         if (ntf >= (int64_t)1 << 31) return hipErrorInvalidValue;
         f.n_tiles = (int)ntf;
-        // certification factor: chain = vertical march (2 ops/row) + the
-        // horizontal sums; nterms = (kh+1)(kw+1)
+        // certification factor of the tile's march and sums along the row
         const double th_ext = (double)(TH - 1) * g.sh + g.kh;
-        const double chain = 2.0 * th_ext + 2.0 * g.kw + 2.0 * L.R + 2.0;
-        const double nterms = (double)(g.kh + 1) * (g.kw + 1);
-        f.cert_g = cert_factor(mode, (double)g.kh * g.kw, chain, nterms);
+        f.cert_g = fast2d_cert(mode, L.R, g.kh, g.kw, th_ext);
         const int gridf = (int)((ntf + wpb_f - 1) / wpb_f);
         if (mode == MODE_U8) return launch_fast2d_modeu8(f, L.R, g.kw, vec, gridf, wpb_f, smem_f, s);
         if (mode == MODE_U16) return launch_fast2d_modeu16(f, L.R, g.kw, vec, gridf, wpb_f, smem_f, s);

@@ -22,6 +22,7 @@
 #include <type_traits>
 
 #include "swc_device.hpp"
+#include "swc_internal.h"
 
 namespace swc {
 
@@ -57,18 +58,59 @@ __host__ __device__ constexpr int fast2d_ring_bytes(int mode, int R, int kh)
            (2 * (((mode == MODE_U8 ? 1 : (mode == MODE_U16 ? 2 : 4)) * R + 3) / 4) +
             ((mode == MODE_F64) ? 1 : 0));
 }
+// Windows that reach more than two lanes to either side (k_w/2 > 2R) take
+// their sums along the row from prefix sums over the wave's columns, kept in
+// a per-wave LDS row of R (64 + 1) entries per channel.  (Each output then
+// costs two LDS entries read and one written, which the LDS bandwidth of a
+// CU makes dearer than the hop-by-hop exchange up to two hops.)
+__host__ __device__ constexpr bool fast2d_prefix(int R, int kw)
+{
+    return kw / 2 > 2 * R || kw - 1 - kw / 2 > 2 * R;
+}
+__host__ __device__ constexpr int fast2d_col_bytes(int mode)
+{
+    return mode == MODE_U8 ? 20 : (mode == MODE_U16 ? 32 : 48);
+}
+__host__ __device__ constexpr int fast2d_prefix_entries(int R) { return R * (kWave + 1); }
+__host__ __device__ constexpr int fast2d_prefix_bytes(int mode, int R, int kw)
+{
+    return fast2d_prefix(R, kw) ? ((fast2d_col_bytes(mode) * fast2d_prefix_entries(R) + 15) & ~15)
+                                : 0;
+}
 // Wide windows: the tile code reads the row leaving the window a second time
 // (it is k_h rows behind the entering one, mostly an Infinity Cache hit)
 // instead of parking k_h rows in LDS, where a ring above 24 KB per wave
-// (taking k_h = k_w) would hold the resident waves per CU below six.  Vector
-// row loads only (the leaving row is read like the entering one).
+// (taking k_h = k_w) would hold the resident waves per CU below six; so do
+// windows whose prefix row and ring together would pass 16 KB per wave (the
+// integer kernels keep three waves per SIMD, which that would not allow).
+// Vector row loads only (the leaving row is read like the entering one).
 __host__ __device__ constexpr bool fast2d_reread(int mode, int R, int KW, bool vec)
 {
-    return vec && fast2d_ring_bytes(mode, R, KW) > 24 * 1024;
+    return vec && (fast2d_ring_bytes(mode, R, KW) > 24 * 1024 ||
+                   (fast2d_prefix(R, KW) &&
+                    fast2d_ring_bytes(mode, R, KW) + fast2d_prefix_bytes(mode, R, KW) > 16 * 1024));
+}
+__host__ __device__ inline int fast2d_ring_region(int mode, int R, int kh, int kw, bool vec)
+{
+    return fast2d_reread(mode, R, kw, vec) ? 0 : ((fast2d_ring_bytes(mode, R, kh) + 15) & ~15);
 }
 __host__ __device__ inline int fast2d_lds_per_wave(int mode, int R, int kh, int kw, bool vec)
 {
-    return fast2d_reread(mode, R, kw, vec) ? 0 : ((fast2d_ring_bytes(mode, R, kh) + 15) & ~15);
+    return fast2d_ring_region(mode, R, kh, kw, vec) + fast2d_prefix_bytes(mode, R, kw);
+}
+
+// Certification factor (float input) of the sums of a tile that marches
+// th_ext input rows: chain = operations on any partial sum (2 per marched
+// row, then the sums along the row), nterms bounds the elements a partial
+// sum holds.  The prefix form sums every column of the wave (in-lane
+// totals and prefixes, a six-step scan, one difference).
+__host__ inline double fast2d_cert(int mode, int R, int kh, int kw, double th_ext)
+{
+    if (fast2d_prefix(R, kw))
+        return cert_factor(mode, (double)kh * kw, 2.0 * th_ext + 2.0 * R + 10.0,
+                           (double)(kh + 1) * (kWave * R + 1));
+    return cert_factor(mode, (double)kh * kw, 2.0 * th_ext + 2.0 * kw + 2.0 * R + 2.0,
+                       (double)(kh + 1) * (kw + 1));
 }
 
 // Output columns per tile when outputs are lane-aligned (unit column step,
@@ -524,15 +566,125 @@ template <int R, int KW> __device__ __forceinline__ float reach_max(float v)
     return fmaxf(ml, mr);
 }
 
+// ---- prefix form for wide windows ----------------------------------------
+// 32-bit integer channels wrap modulo 2^32 here: a prefix over the wave's
+// columns may pass 2^31, the window sums themselves do not, so their
+// differences are exact.
+__device__ __forceinline__ int wrap_add(int a, int b) { return (int)((uint32_t)a + (uint32_t)b); }
+__device__ __forceinline__ int wrap_sub(int a, int b) { return (int)((uint32_t)a - (uint32_t)b); }
+__device__ __forceinline__ uint32_t wrap_add(uint32_t a, uint32_t b) { return a + b; }
+__device__ __forceinline__ uint32_t wrap_sub(uint32_t a, uint32_t b) { return a - b; }
+__device__ __forceinline__ double wrap_add(double a, double b) { return a + b; }
+__device__ __forceinline__ double wrap_sub(double a, double b) { return a - b; }
+
+// Every channel of a Col at once (F(field, field of b) for each field).
+template <int M, class F> __device__ __forceinline__ void col_each(Col<M>& a, const Col<M>& b, F&& f)
+{
+    f(a.x, b.x); f(a.y, b.y); f(a.xx, b.xx); f(a.yy, b.yy);
+    if constexpr (M == MODE_F64) { f(a.xy, b.xy); f(a.miss, b.miss); }
+    else f(a.xy2, b.xy2);
+}
+
+// One step of the wavefront scan on every channel: a += a of the lane the
+// DPP control names (zero where it names none).
+template <int CTRL, int RMASK, bool BC, int M> __device__ __forceinline__ void col_scan_step(Col<M>& a)
+{
+    col_each<M>(a, a, [](auto& d, const auto& v) __attribute__((always_inline)) {
+        d = wrap_add(d, dppv<CTRL, RMASK, BC>(v));
+    });
+}
+
+// Entry of prefix column c = R*l + i (0 <= i < R, 0 <= l <= 64) in the LDS
+// row: blocks of 65 entries by i, so the 64 lanes of a wave touch 64
+// consecutive entries of every channel array.
+__device__ __forceinline__ int prefix_entry(int i, int l) { return i * (kWave + 1) + l; }
+
+// The row holds one array per channel, fast2d_prefix_entries(R) entries
+// each, in field order.
+template <int M, int R, class F>
+__device__ __forceinline__ void col_lds_each(char* base, int e, Col<M>& a, F&& f)
+{
+    constexpr int NE = fast2d_prefix_entries(R);
+    int off = 0;
+    col_each<M>(a, a, [&](auto& d, const auto&) __attribute__((always_inline)) {
+        using FT = std::remove_reference_t<decltype(d)>;
+        f(d, (FT*)(base + off) + e);
+        off += (int)sizeof(FT) * NE;
+    });
+}
+
+// Window sums of one output row when the window reaches beyond the adjacent
+// lanes: P[c] = sum of the wave's columns left of column c, from the lane's
+// column total, a DPP wavefront scan of the totals and the in-lane prefix;
+// the lanes write P of their columns (lane 63 also P[64 R]) to the LDS row,
+// and output j of lane t is P[R t + j + RH + 1] - P[R t + j - LH].  Outputs
+// whose window passes the wave's ends (halo lanes, never stored) read
+// clamped entries.  `prow`: this wave's LDS row.
+template <int M, int R, int KW, class Emit>
+__device__ __forceinline__ void hsum_prefix(const Col<M> (&V)[R], Emit&& emit, char* prow)
+{
+    static_assert(sizeof(Col<M>) == fast2d_col_bytes(M), "channel layout");
+    constexpr int LH = KW / 2;
+    constexpr int RH = KW - 1 - LH;
+    const int lane = threadIdx.x & (kWave - 1);
+    Col<M> T = V[0];
+#pragma unroll
+    for (int j = 1; j < R; j++)
+        col_each<M>(T, V[j], [](auto& d, const auto& v) __attribute__((always_inline)) { d = wrap_add(d, v); });
+    Col<M> I = T;
+    col_scan_step<0x111, 0xf, true>(I);     // row_shr:1
+    col_scan_step<0x112, 0xf, true>(I);     // row_shr:2
+    col_scan_step<0x114, 0xf, true>(I);     // row_shr:4
+    col_scan_step<0x118, 0xf, true>(I);     // row_shr:8
+    col_scan_step<0x142, 0xa, false>(I);    // row_bcast:15 -> rows 1, 3
+    col_scan_step<0x143, 0xc, false>(I);    // row_bcast:31 -> rows 2, 3
+    Col<M> P = col_dpp<true, M>(I);         // columns of the lanes to the left
+#pragma unroll
+    for (int j = 0; j < R; j++) {
+        if (j > 0)
+            col_each<M>(P, V[j - 1], [](auto& d, const auto& v) __attribute__((always_inline)) { d = wrap_add(d, v); });
+        col_lds_each<M, R>(prow, prefix_entry(j, lane), P,
+                           [](auto& d, auto* q) __attribute__((always_inline)) { *q = d; });
+    }
+    if (lane == kWave - 1)
+        col_lds_each<M, R>(prow, prefix_entry(0, kWave), I,
+                           [](auto& d, auto* q) __attribute__((always_inline)) { *q = d; });
+    wave_lds_sync();
+    // every read is issued before the first difference is needed, so the
+    // LDS latency is paid once per row
+    Col<M> A[R], S[R];
+#pragma unroll
+    for (int j = 0; j < R; j++) {
+        // left end: column R t + j - LH; right end + 1: R t + j + RH + 1
+        const int dl = j - LH, dr = j + RH + 1;
+        const int il = ((dl % R) + R) % R, ir = dr % R;
+        const int tl = lane + (dl - il) / R, tr = lane + (dr - ir) / R;
+        const int el = tl < 0 ? prefix_entry(0, 0) : prefix_entry(il, tl);
+        const int er = (tr > kWave || (tr == kWave && ir != 0)) ? prefix_entry(0, kWave)
+                                                                 : prefix_entry(ir, tr);
+        col_lds_each<M, R>(prow, el, A[j], [](auto& d, auto* q) __attribute__((always_inline)) { d = *q; });
+        col_lds_each<M, R>(prow, er, S[j], [](auto& d, auto* q) __attribute__((always_inline)) { d = *q; });
+    }
+#pragma unroll
+    for (int j = 0; j < R; j++) {
+        col_each<M>(S[j], A[j], [](auto& d, const auto& v) __attribute__((always_inline)) { d = wrap_sub(d, v); });
+        emit(j, S[j]);
+    }
+    // the next row's writes must not pass this row's reads of other lanes
+    wave_lds_sync();
+}
+
 // Window sums of one output row, whichever form fits the window width
-// (EARLY: see hsum_onehop).
+// (EARLY: see hsum_onehop; prow: the LDS row of the prefix form).
 template <int M, int R, int KW, bool EARLY, class Emit>
-__device__ __forceinline__ void hsum_row(const Col<M> (&V)[R], Emit&& emit)
+__device__ __forceinline__ void hsum_row(const Col<M> (&V)[R], Emit&& emit, char* prow)
 {
     if constexpr (hsum_two_phase<M, R, KW>())
         hsum_twophase<M, R, KW>(V, emit);
     else if constexpr (hsum_one_hop<M, R, KW>())
         hsum_onehop<M, R, KW, EARLY>(V, emit);
+    else if constexpr (fast2d_prefix(R, KW))
+        hsum_prefix<M, R, KW>(V, emit, prow);
     else
         hslide<M, R, KW>(V, emit);
 }
@@ -685,6 +837,8 @@ __device__ __forceinline__ void tile2d(const P2DF& g, const int tile, char* smem
     };
     constexpr bool kReread = fast2d_reread(M, R, KW, VEC);
     uint32_t* ringx = (uint32_t*)smem;
+    // LDS row of the prefix form (wide windows), after the ring
+    char* const prow = smem + (kReread ? 0 : ((fast2d_ring_bytes(M, R, kh) + 15) & ~15));
     uint32_t* ringy = ringx + kh * kWave * NW;
     int* ringm = (int*)(ringy + kh * kWave * NW);                // [kh][64] (float input)
     if constexpr (!kReread) {
@@ -765,9 +919,16 @@ __device__ __forceinline__ void tile2d(const P2DF& g, const int tile, char* smem
         double gx = 0.0, gy = 0.0;   // certification thresholds (float input)
         if constexpr (kFloat) {
             // M covers every column any window sum of this lane touched:
-            // the lanes t - reach_l .. t + reach_r
-            const double Mx = (double)reach_max<R, KW>(hmx);
-            const double My = (double)reach_max<R, KW>(hmy);
+            // the lanes t - reach_l .. t + reach_r (the prefix form sums
+            // every column of the wave: the wave's maximum)
+            double Mx, My;
+            if constexpr (fast2d_prefix(R, KW)) {
+                Mx = (double)wave_max(hmx);
+                My = (double)wave_max(hmy);
+            } else {
+                Mx = (double)reach_max<R, KW>(hmx);
+                My = (double)reach_max<R, KW>(hmy);
+            }
             gx = g.cert_g * Mx * Mx;
             gy = g.cert_g * My * My;
         }
@@ -852,7 +1013,7 @@ __device__ __forceinline__ void tile2d(const P2DF& g, const int tile, char* smem
             // costs registers
             if ((j % SWC_FAST2D_EPI_GROUP) == SWC_FAST2D_EPI_GROUP - 1)
                 __builtin_amdgcn_sched_barrier(0);
-        });
+        }, prow);
         // rare path: exact decisions (integer input) / two-pass recomputation
         // (float input) for the outputs whose fast result is not certified.
         // The window sums are recomputed (the slide is deterministic), so the
@@ -889,7 +1050,7 @@ __device__ __forceinline__ void tile2d(const P2DF& g, const int tile, char* smem
                         cvals[j] = N < 0.0 ? -f : f;
                     }
                 }
-            });
+            }, prow);
         }
     };
 

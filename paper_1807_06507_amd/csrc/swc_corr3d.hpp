@@ -409,9 +409,10 @@ __device__ __forceinline__ void tile3d(const P3D& g, const int tile, char* smem)
 #pragma unroll
         for (int t = 0; t < TY; t++) {
             if (t >= pyn) continue;
+            static_assert(!fast2d_prefix(R, KW), "3-D x windows stay within one hop");
             hsum_row<M, R, KW, false>(VY[t], [&](int j, const Col<M>& S) __attribute__((always_inline)) {
                 slot(t, j).add(lane, S);
-            });
+            }, nullptr);
         }
         if (li != next_ready) continue;
         next_ready += g.sz;

@@ -288,6 +288,60 @@ template <int M> __device__ __forceinline__ Acc<M> lds_get(const LdsRow<M>& r, i
     return a;
 }
 
+// ---- wavefront inclusive scan (64 lanes) via DPP -------------------------
+template <int CTRL, int RMASK, bool BC>
+__device__ __forceinline__ uint32_t dppm(uint32_t v)
+{
+    return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, CTRL, RMASK, 0xf, BC);
+}
+
+template <int CTRL, int RMASK, bool BC, class V> __device__ __forceinline__ V dppv(V v)
+{
+    constexpr int NW = sizeof(V) / 4;
+    uint32_t w[NW];
+    __builtin_memcpy(w, &v, sizeof(V));
+#pragma unroll
+    for (int i = 0; i < NW; i++) w[i] = dppm<CTRL, RMASK, BC>(w[i]);
+    V r;
+    __builtin_memcpy(&r, w, sizeof(V));
+    return r;
+}
+
+// Inclusive prefix sum over the 64 lanes (lane order).
+template <class V> __device__ __forceinline__ V wave_incl_scan(V v)
+{
+    v += dppv<0x111, 0xf, true>(v);   // row_shr:1
+    v += dppv<0x112, 0xf, true>(v);   // row_shr:2
+    v += dppv<0x114, 0xf, true>(v);   // row_shr:4
+    v += dppv<0x118, 0xf, true>(v);   // row_shr:8
+    v += dppv<0x142, 0xa, false>(v);  // row_bcast:15 -> rows 1, 3
+    v += dppv<0x143, 0xc, false>(v);  // row_bcast:31 -> rows 2, 3
+    return v;
+}
+
+template <class V> __device__ __forceinline__ V lane63(V v)
+{
+    constexpr int NW = sizeof(V) / 4;
+    uint32_t w[NW];
+    __builtin_memcpy(w, &v, sizeof(V));
+#pragma unroll
+    for (int i = 0; i < NW; i++) w[i] = (uint32_t)__builtin_amdgcn_readlane((int)w[i], 63);
+    V r;
+    __builtin_memcpy(&r, w, sizeof(V));
+    return r;
+}
+
+__device__ __forceinline__ float wave_max(float v)
+{
+    v = fmaxf(v, __uint_as_float(dppm<0x111, 0xf, true>(__float_as_uint(v))));
+    v = fmaxf(v, __uint_as_float(dppm<0x112, 0xf, true>(__float_as_uint(v))));
+    v = fmaxf(v, __uint_as_float(dppm<0x114, 0xf, true>(__float_as_uint(v))));
+    v = fmaxf(v, __uint_as_float(dppm<0x118, 0xf, true>(__float_as_uint(v))));
+    v = fmaxf(v, __uint_as_float(dppm<0x142, 0xa, false>(__float_as_uint(v))));
+    v = fmaxf(v, __uint_as_float(dppm<0x143, 0xc, false>(__float_as_uint(v))));
+    return __uint_as_float((uint32_t)__builtin_amdgcn_readlane((int)__float_as_uint(v), 63));
+}
+
 // Order LDS traffic of one wavefront (writes by some lanes, reads by others).
 __device__ __forceinline__ void wave_lds_sync()
 {
