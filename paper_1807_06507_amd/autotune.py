@@ -188,8 +188,11 @@ def main():
         emit("f32", 1, 0, kbucket(1001), b[1])
     if only is None or "c4a" in only:
         x, y = volume_3d((256, 512, 512), seed=4)
-        cand3 = [(4, th, w, 0, ty) for th, w, ty in itertools.product([16, 24, 32, 48, 64], [1, 2, 4],
-                                                                      [2, 4])]
+        # planes per wave: besides round numbers, heights that make the
+        # 512 x 512 x 256 volume's tiles fill a whole number of resident
+        # rounds (43: six z tiles, 86: three)
+        cand3 = [(4, th, w, 0, ty) for th, w, ty in itertools.product(
+            [16, 24, 32, 43, 48, 64, 86, 128], [1, 2, 4], [2, 4]) if ty == 2 or th in (32, 64)]
         b = tune_single(x, y, (7, 7, 7), 1, "clip", cand3, "f32 3-D k7")
         emit("f32", 3, 0, 7, b[1])
     # merge: lines of classes not tuned in this run are kept as they were

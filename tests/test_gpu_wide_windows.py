@@ -10,6 +10,9 @@ oracle (through the C ABI).
   later constant-x patch's windows reach from two or more lanes away; the
   oracle flags those windows ZVAR_X (Section 3, all-equal windows), and so
   must the GPU.
+* The prefix form (windows reaching more than two lanes): its sums are
+  differences of prefixes over the whole wave, so the bound takes the
+  wave's largest value; a case plants 1e6 far left of a constant patch.
 * Every compiled wide variant (R = 4 and 8 columns per lane, k_w = 15 and 31,
   u8 / u16 / f32) on several tiles with ragged tails, borders, missing values
   and constant patches: bit-exact for integers, flags identical and
@@ -83,6 +86,29 @@ def test_certification_reaches_every_window_lane(k, R):
         _noflag_compare(x, y, (k, k), 1, border, params=params, tag=f"cert-reach k={k} R={R}")
     # default launch parameters (tile height from the resident-wave count)
     compare(x, y, (k, k), 1, "clip", tag=f"cert-reach k={k} default")
+
+
+def test_certification_prefix_form_wave_wide():
+    """Windows reaching more than two lanes (k = 31 at R = 4) take their sums
+    as differences of prefixes over every column of the wave to their left.
+    Values of 1e6 far to the left of a constant-x patch, in the same rows,
+    then leave rounding in the patch's sums although no patch window holds
+    them: the bound must take the wave's largest value, and the oracle's
+    ZVAR_X flags must come back."""
+    k = 31
+    rng = np.random.default_rng(7)
+    H, W = 160, 300
+    x = rng.standard_normal((H, W)).astype(np.float32)
+    y = rng.standard_normal((H, W)).astype(np.float32)
+    r0, r1, c0, c1 = 40, 120, 150, 230
+    x[r0:r1, c0:c1] = 5.0
+    x[r0 - 20:r1 + 20, 40:52] = 1e6
+    _, _, ofl = oracle.corr(x, y, (k, k), 1, "clip")
+    assert int(np.count_nonzero(ofl & 4)) > 0, "the patch must produce constant-x windows"
+    for border in ("clip", "fill"):
+        compare(x, y, (k, k), 1, border, params=(4, 256, 1), tag="prefix-cert")
+        _noflag_compare(x, y, (k, k), 1, border, params=(4, 256, 1), tag="prefix-cert")
+    compare(x, y, (k, k), 1, "clip", tag="prefix-cert default")
 
 
 def test_certification_reach_batched():
