@@ -305,6 +305,7 @@ def window_step_sweep(torch, swc, sets, dtype, w, stream, reps=20):
 
             def run(i):
                 go[i % len(go)]()
+            _settle(torch, run, 0.1)
             for i in range(3 * len(go)):
                 run(i)
             _, ms = _timed_region(torch, stream, reps, run)
