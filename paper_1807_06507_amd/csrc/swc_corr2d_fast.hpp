@@ -51,12 +51,11 @@ __host__ __device__ inline bool fast2d_supported(int mode, int R, int KW)
     return false;
 }
 
-// LDS bytes per wave: the raw-row ring (k_h rows).
+// LDS bytes per wave: the raw-row ring (k_h rows of x and y as read; the
+// missing positions of a float row are found again when it leaves).
 __host__ __device__ constexpr int fast2d_ring_bytes(int mode, int R, int kh)
 {
-    return kh * kWave * 4 *
-           (2 * (((mode == MODE_U8 ? 1 : (mode == MODE_U16 ? 2 : 4)) * R + 3) / 4) +
-            ((mode == MODE_F64) ? 1 : 0));
+    return kh * kWave * 4 * (2 * (((mode == MODE_U8 ? 1 : (mode == MODE_U16 ? 2 : 4)) * R + 3) / 4));
 }
 // Windows that reach more than two lanes to either side (k_w/2 > 2R) take
 // their sums along the row from prefix sums over the wave's columns, kept in
@@ -840,7 +839,6 @@ __device__ __forceinline__ void tile2d(const P2DF& g, const int tile, char* smem
     // LDS row of the prefix form (wide windows), after the ring
     char* const prow = smem + (kReread ? 0 : ((fast2d_ring_bytes(M, R, kh) + 15) & ~15));
     uint32_t* ringy = ringx + kh * kWave * NW;
-    int* ringm = (int*)(ringy + kh * kWave * NW);                // [kh][64] (float input)
     if constexpr (!kReread) {
         for (int s = 0; s < kh; s++) {
 #pragma unroll
@@ -848,7 +846,6 @@ __device__ __forceinline__ void tile2d(const P2DF& g, const int tile, char* smem
                 ringx[ring_at(s, i)] = 0u;
                 ringy[ring_at(s, i)] = 0u;
             }
-            if constexpr (kFloat) ringm[s * kWave + lane] = 0;
         }
     }
 
@@ -1149,6 +1146,7 @@ __device__ __forceinline__ void tile2d(const P2DF& g, const int tile, char* smem
         int64_t orow = (int64_t)(up ? p0 + ph - 1 : p0) * (int64_t)g.OW;
         const int64_t orow_step = up ? -(int64_t)g.OW : (int64_t)g.OW;
         int slot = 0;
+        bool dirty = false;      // wave-uniform: a missing value has entered the tile
         int next_ready = kh - 1;
         int p = up ? p0 + ph - 1 : p0;
         const int pstep = up ? -1 : 1;
@@ -1206,6 +1204,16 @@ __device__ __forceinline__ void tile2d(const P2DF& g, const int tile, char* smem
                         oy[i] = ringy[ring_at(slot, i)];
                     }
                 }
+                if constexpr (!kReread) {
+                    // the entering row as read (same lane, same address: the
+                    // reads above return the old row)
+#pragma unroll
+                    for (int i = 0; i < NW; i++) {
+                        ringx[ring_at(slot, i)] = wx[i];
+                        ringy[ring_at(slot, i)] = wy[i];
+                    }
+                    slot = (slot + 1 == kh) ? 0 : slot + 1;
+                }
                 int omiss = 0, nmiss = 0;
                 T ax[R], ay[R], bx[R], by[R];
                 __builtin_memcpy(ax, wx, sizeof(T) * R);
@@ -1216,10 +1224,11 @@ __device__ __forceinline__ void tile2d(const P2DF& g, const int tile, char* smem
                     // positions outside the array read zero and are never
                     // missing, whatever the threshold
                     const bool row_in = (unsigned)row < (unsigned)H;
-                    if constexpr (kReread) {
-                        // the leaving row's missing positions, found again
-                        // (rows outside the array, and the first k_h rows of
-                        // the march, read zero and are never missing)
+                    // the leaving row's missing positions, found again (rows
+                    // outside the array, and the first k_h rows of the march,
+                    // read zero and are never missing); none while no missing
+                    // value has entered the tile
+                    if (kReread || dirty) {
                         const int rowo = up ? row + kh : row - kh;
                         const bool rowo_in = li >= kh && (unsigned)rowo < (unsigned)H;
 #pragma unroll
@@ -1231,8 +1240,6 @@ __device__ __forceinline__ void tile2d(const P2DF& g, const int tile, char* smem
                             by[j] = m ? 0.f : by[j];
                             omiss |= m ? (1 << j) : 0;
                         }
-                    } else {
-                        omiss = ringm[slot * kWave + lane];
                     }
 #pragma unroll
                     for (int j = 0; j < R; j++) {
@@ -1245,18 +1252,7 @@ __device__ __forceinline__ void tile2d(const P2DF& g, const int tile, char* smem
                         hmx = fmaxf(hmx, __builtin_fabsf(ax[j]));
                         hmy = fmaxf(hmy, __builtin_fabsf(ay[j]));
                     }
-                    __builtin_memcpy(wx, ax, sizeof(T) * R);
-                    __builtin_memcpy(wy, ay, sizeof(T) * R);
-                    if constexpr (!kReread) ringm[slot * kWave + lane] = nmiss;
-                }
-                if constexpr (!kReread) {
-                    // same lane, same address: the read above returns the old row
-#pragma unroll
-                    for (int i = 0; i < NW; i++) {
-                        ringx[ring_at(slot, i)] = wx[i];
-                        ringy[ring_at(slot, i)] = wy[i];
-                    }
-                    slot = (slot + 1 == kh) ? 0 : slot + 1;
+                    if constexpr (!kReread) dirty = dirty || __builtin_amdgcn_ballot_w64(nmiss != 0) != 0;
                 }
                 // ---- step 2: running column sums ----
 #pragma unroll
