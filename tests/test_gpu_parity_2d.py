@@ -74,6 +74,27 @@ def test_parity_float_missing_and_constant():
             compare(x, y, window, step, border, tag="float-specials")
 
 
+def test_parity_float_missing_enters_mid_march():
+    """Float rows are parked in the LDS ring as read; a leaving row's missing
+    positions are found again only once a missing value has entered the
+    tile.  Missing values that first appear deep in a tile's march (one tile
+    per column band, 256-row tiles), leave its windows again, and a threshold
+    of 0 (zeros then missing, while the ring's initial zeros and positions
+    outside the array are not): every output against the oracle, for every
+    window width the ring serves."""
+    x, y = random_pair((200, 300), "f32", seed=31, kind="lognormal")
+    x[90, 40] = -1000.0
+    y[120, 200:204] = np.nan
+    x[150, 290] = -np.inf
+    for k in (3, 5, 7, 9):
+        compare(x, y, (k, k), 1, "clip", params=(4, 256, 1), tag="float-missing-late")
+        compare(x, y, (k, k), 1, "fill", tag="float-missing-late")
+    z = x.copy()
+    z[100:103, 50:60] = 0.0
+    compare(z, y, (7, 7), 1, "clip", params=(4, 256, 1), missing_le=0.0, tag="float-missing-late-thr0")
+    compare(z, y, (9, 9), 1, "fill", params=(4, 256, 1), missing_le=0.0, tag="float-missing-late-thr0")
+
+
 def test_parity_offset_data_cancellation():
     """x ~ N(1000, 1): the sums cancel heavily; still within 2^-24."""
     for window in ((3, 3), (7, 7), (15, 15), (31, 31)):
