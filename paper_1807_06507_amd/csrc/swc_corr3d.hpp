@@ -76,6 +76,24 @@ __device__ __forceinline__ Col<M> col_delta(T a, T b, T ao, T bo, int m, int mo)
     return d;
 }
 
+// a += col_delta(a, b, ao, bo) without forming the difference first: the
+// product channels take the entering and leaving products as two FMAs into
+// the sum (two roundings, as the difference and its addition have).
+template <int M, class T>
+__device__ __forceinline__ void col_accum_delta(Col<M>& s, T a, T b, T ao, T bo)
+{
+    if constexpr (M == MODE_F64) {
+        const double x = (double)a, y = (double)b, xo = (double)ao, yo = (double)bo;
+        s.x += x - xo;
+        s.y += y - yo;
+        s.xx = __builtin_fma(x, x, __builtin_fma(-xo, xo, s.xx));
+        s.yy = __builtin_fma(y, y, __builtin_fma(-yo, yo, s.yy));
+        s.xy = __builtin_fma(x, y, __builtin_fma(-xo, yo, s.xy));
+    } else {
+        col_update_int<M>(s, (int)a, (int)b, (int)ao, (int)bo);
+    }
+}
+
 // LDS bytes per wave for the running 3-D sums (TY rows x R columns).
 template <int M, int TY> __host__ __device__ constexpr int tile3d_lds_per_wave(int R)
 {
@@ -723,16 +741,13 @@ __device__ __forceinline__ void tile3d_cube(const P3D& g, const int tile, char* 
             }
 #pragma unroll
             for (int j = 0; j < R; j++) {
-                const Col<M> d = col_delta<M, T>(ax[j], ay[j], bx[j], by[j], 0, 0);
                 if (r == 0) {
-                    V0[j] = d;
+                    V0[j] = col_delta<M, T>(ax[j], ay[j], bx[j], by[j], 0, 0);
                 } else if (r == 1) {
-                    MID[j] = d;
-                } else if (r < KW) {
-                    col_add<M>(MID[j], d);
+                    MID[j] = col_delta<M, T>(ax[j], ay[j], bx[j], by[j], 0, 0);
                 } else {
-                    col_add<M>(V0[j], MID[j]);
-                    col_add<M>(MID[j], d);
+                    if (r == KW) col_add<M>(V0[j], MID[j]);
+                    col_accum_delta<M, T>(MID[j], ax[j], ay[j], bx[j], by[j]);
                 }
             }
             __builtin_amdgcn_sched_barrier(0);
