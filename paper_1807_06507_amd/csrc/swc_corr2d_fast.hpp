@@ -612,8 +612,8 @@ __device__ __forceinline__ void col_lds_each(char* base, int e, Col<M>& a, F&& f
     });
 }
 
-// Window sums of one output row when the window reaches beyond the adjacent
-// lanes: P[c] = sum of the wave's columns left of column c, from the lane's
+// Window sums of one output row when the window reaches more than two lanes
+// to a side: P[c] = sum of the wave's columns left of column c, from the lane's
 // column total, a DPP wavefront scan of the totals and the in-lane prefix;
 // the lanes write P of their columns (lane 63 also P[64 R]) to the LDS row,
 // and output j of lane t is P[R t + j + RH + 1] - P[R t + j - LH].  Outputs
