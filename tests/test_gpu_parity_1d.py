@@ -41,6 +41,31 @@ def test_parity_1d_missing_and_constant():
         compare(x, y, (k,), 1, "fill", tag="1d-specials")
 
 
+def test_parity_1d_missing_enters_late():
+    """Missing values that first enter a wave's span after many clean rows
+    (the leaving values are looked at one by one only from then on), in the
+    initial window of a span, and a threshold of 0 (zeros missing; positions
+    outside the series are not): every output, ring and re-read paths, and
+    several waves per series (short spans)."""
+    import paper_1807_06507_amd as swc
+    x, y = random_pair((90000,), "f32", seed=8, kind="lognormal")
+    x[40000] = -5000.0
+    y[61234:61240] = np.nan
+    x[88000] = -np.inf
+    for k in (5, 101, 1001):
+        for params in (None, (8, 4, 1)):
+            compare(x, y, (k,), 1, "clip", params=params, tag="1d-missing-late")
+        compare(x, y, (k,), 1, "fill", tag="1d-missing-late")
+    swc.set_debug(4)
+    try:
+        compare(x, y, (1001,), 1, "clip", tag="1d-missing-late-reread")
+    finally:
+        swc.set_debug(0)
+    z = x.copy()
+    z[30000:30010] = 0.0
+    compare(z, y, (101,), 1, "fill", params=(8, 4, 1), missing_le=0.0, tag="1d-missing-thr0")
+
+
 @pytest.mark.parametrize("dtype", ["u8", "u16"])
 def test_parity_1d_integer_constant_runs(dtype):
     rng = np.random.default_rng(11)
