@@ -565,6 +565,93 @@ template <int R, int KW> __device__ __forceinline__ float reach_max(float v)
     return fmaxf(ml, mr);
 }
 
+// ---- two-hop windows --------------------------------------------------------
+// A word of the lane `h` lanes to the left (h > 0) or right (h < 0), through
+// the LDS crossbar (ds_bpermute, one instruction whatever the distance).
+// Lanes whose source lies beyond the wave's ends get a wrapped-around word;
+// the callers use it only in halo lanes, which store no output.
+template <int H, class V> __device__ __forceinline__ V lane_from(V v)
+{
+    static_assert(sizeof(V) % 4 == 0, "32-bit multiples only");
+    constexpr int NW = sizeof(V) / 4;
+    const int lane = threadIdx.x & (kWave - 1);
+    const int addr = ((lane - H) & (kWave - 1)) << 2;
+    uint32_t w[NW];
+    __builtin_memcpy(w, &v, sizeof(V));
+#pragma unroll
+    for (int i = 0; i < NW; i++) w[i] = (uint32_t)__builtin_amdgcn_ds_bpermute(addr, (int)w[i]);
+    V r;
+    __builtin_memcpy(&r, w, sizeof(V));
+    return r;
+}
+template <int H, int M> __device__ __forceinline__ Col<M> col_from(const Col<M>& a)
+{
+    Col<M> r = a;
+    col_each<M>(r, a, [](auto& d, const auto& v) __attribute__((always_inline)) { d = lane_from<H>(v); });
+    return r;
+}
+
+// Window sums of one output row when the window reaches exactly two lanes
+// to a side (R <= k_w/2 - (R-1) and k_w/2 <= 2R, likewise to the right): every
+// output's window holds the whole adjacent lanes and a part of the next ones.
+// Output j = (suffix of lane t-2) + T(t-1) + T(t) + T(t+1) + (prefix of lane
+// t+2): the lane totals of the neighbours move one hop by DPP, the partial
+// sums two hops through the LDS crossbar (one instruction per word instead
+// of two DPP moves).  Additions only; no partial sum holds a column outside
+// the output's window.
+template <int M, int R, int KW>
+__host__ __device__ constexpr bool hsum_two_hop()
+{
+    return KW / 2 - (R - 1) >= R && KW / 2 - R <= R - 1 &&
+           (KW - 1 - KW / 2) - (R - 1) >= R && (KW - 1 - KW / 2) - R <= R - 1 &&
+           (KW / 2 > R || KW - 1 - KW / 2 > R);
+}
+
+template <int M, int R, int KW, class Emit>
+__device__ __forceinline__ void hsum_twohop(const Col<M> (&V)[R], Emit&& emit)
+{
+    constexpr int LH = KW / 2;
+    constexpr int RH = KW - 1 - LH;
+    constexpr int MS = LH - R;        // columns of lane t-2 in output 0's window
+    constexpr int MP = RH - R;        // columns of lane t+2 in output R-1's window
+    auto add = [](Col<M>& d, const Col<M>& v) __attribute__((always_inline)) {
+        col_each<M>(d, v, [](auto& a, const auto& b) __attribute__((always_inline)) { a = a + b; });
+    };
+    // own suffix sums (last m columns) and prefix sums (first m columns)
+    Col<M> Suf[MS > 0 ? MS : 1], Pre[MP > 0 ? MP : 1];
+    if constexpr (MS > 0) {
+        Suf[0] = V[R - 1];
+#pragma unroll
+        for (int m = 1; m < MS; m++) { Suf[m] = Suf[m - 1]; add(Suf[m], V[R - 1 - m]); }
+    }
+    if constexpr (MP > 0) {
+        Pre[0] = V[0];
+#pragma unroll
+        for (int m = 1; m < MP; m++) { Pre[m] = Pre[m - 1]; add(Pre[m], V[m]); }
+    }
+    // the partial sums leave first (their round trip is the longest)
+    Col<M> L2[MS > 0 ? MS : 1], R2[MP > 0 ? MP : 1];
+#pragma unroll
+    for (int m = 0; m < MS; m++) L2[m] = col_from<2, M>(Suf[m]);
+#pragma unroll
+    for (int m = 0; m < MP; m++) R2[m] = col_from<-2, M>(Pre[m]);
+    Col<M> T = V[0];
+#pragma unroll
+    for (int c = 1; c < R; c++) add(T, V[c]);
+    Col<M> C = col_dpp<true, M>(T);            // T of lane t-1
+    add(C, T);
+    add(C, col_dpp<false, M>(T));              // + T of lane t+1
+#pragma unroll
+    for (int j = 0; j < R; j++) {
+        Col<M> S = C;
+        const int ml = MS - j;                 // columns of lane t-2: LH - j - R
+        const int mr = j + 1 + MP - R;         // columns of lane t+2: RH - (R-1-j) - R
+        if (ml > 0) add(S, L2[ml - 1]);
+        if (mr > 0) add(S, R2[mr - 1]);
+        emit(j, S);
+    }
+}
+
 // ---- prefix form for wide windows ----------------------------------------
 // 32-bit integer channels wrap modulo 2^32 here: a prefix over the wave's
 // columns may pass 2^31, the window sums themselves do not, so their
@@ -649,25 +736,32 @@ __device__ __forceinline__ void hsum_prefix(const Col<M> (&V)[R], Emit&& emit, c
         col_lds_each<M, R>(prow, prefix_entry(0, kWave), I,
                            [](auto& d, auto* q) __attribute__((always_inline)) { *q = d; });
     wave_lds_sync();
-    // every read is issued before the first difference is needed, so the
-    // LDS latency is paid once per row
-    Col<M> A[R], S[R];
+    // float input (two waves per SIMD, registers to spare): every read is
+    // issued before the first difference is needed, so the LDS latency is
+    // paid once per row; integer input (three waves per SIMD) reads output
+    // by output
+    constexpr int NB = (M == MODE_F64) ? R : 1;
 #pragma unroll
-    for (int j = 0; j < R; j++) {
-        // left end: column R t + j - LH; right end + 1: R t + j + RH + 1
-        const int dl = j - LH, dr = j + RH + 1;
-        const int il = ((dl % R) + R) % R, ir = dr % R;
-        const int tl = lane + (dl - il) / R, tr = lane + (dr - ir) / R;
-        const int el = tl < 0 ? prefix_entry(0, 0) : prefix_entry(il, tl);
-        const int er = (tr > kWave || (tr == kWave && ir != 0)) ? prefix_entry(0, kWave)
-                                                                 : prefix_entry(ir, tr);
-        col_lds_each<M, R>(prow, el, A[j], [](auto& d, auto* q) __attribute__((always_inline)) { d = *q; });
-        col_lds_each<M, R>(prow, er, S[j], [](auto& d, auto* q) __attribute__((always_inline)) { d = *q; });
-    }
+    for (int j0 = 0; j0 < R; j0 += NB) {
+        Col<M> A[NB], S[NB];
 #pragma unroll
-    for (int j = 0; j < R; j++) {
-        col_each<M>(S[j], A[j], [](auto& d, const auto& v) __attribute__((always_inline)) { d = wrap_sub(d, v); });
-        emit(j, S[j]);
+        for (int b = 0; b < NB; b++) {
+            const int j = j0 + b;
+            // left end: column R t + j - LH; right end + 1: R t + j + RH + 1
+            const int dl = j - LH, dr = j + RH + 1;
+            const int il = ((dl % R) + R) % R, ir = dr % R;
+            const int tl = lane + (dl - il) / R, tr = lane + (dr - ir) / R;
+            const int el = tl < 0 ? prefix_entry(0, 0) : prefix_entry(il, tl);
+            const int er = (tr > kWave || (tr == kWave && ir != 0)) ? prefix_entry(0, kWave)
+                                                                     : prefix_entry(ir, tr);
+            col_lds_each<M, R>(prow, el, A[b], [](auto& d, auto* q) __attribute__((always_inline)) { d = *q; });
+            col_lds_each<M, R>(prow, er, S[b], [](auto& d, auto* q) __attribute__((always_inline)) { d = *q; });
+        }
+#pragma unroll
+        for (int b = 0; b < NB; b++) {
+            col_each<M>(S[b], A[b], [](auto& d, const auto& v) __attribute__((always_inline)) { d = wrap_sub(d, v); });
+            emit(j0 + b, S[b]);
+        }
     }
     // the next row's writes must not pass this row's reads of other lanes
     wave_lds_sync();
@@ -684,6 +778,8 @@ __device__ __forceinline__ void hsum_row(const Col<M> (&V)[R], Emit&& emit, char
         hsum_onehop<M, R, KW, EARLY>(V, emit);
     else if constexpr (fast2d_prefix(R, KW))
         hsum_prefix<M, R, KW>(V, emit, prow);
+    else if constexpr (M == MODE_F64 && hsum_two_hop<M, R, KW>())
+        hsum_twohop<M, R, KW>(V, emit);      // (the integer kernels' 168 VGPRs spill with it)
     else
         hslide<M, R, KW>(V, emit);
 }
