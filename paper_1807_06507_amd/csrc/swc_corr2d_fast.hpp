@@ -565,6 +565,14 @@ template <int R, int KW> __device__ __forceinline__ float reach_max(float v)
     return fmaxf(ml, mr);
 }
 
+// Every channel of a Col at once (F(field, field of b) for each field).
+template <int M, class F> __device__ __forceinline__ void col_each(Col<M>& a, const Col<M>& b, F&& f)
+{
+    f(a.x, b.x); f(a.y, b.y); f(a.xx, b.xx); f(a.yy, b.yy);
+    if constexpr (M == MODE_F64) { f(a.xy, b.xy); f(a.miss, b.miss); }
+    else f(a.xy2, b.xy2);
+}
+
 // ---- two-hop windows --------------------------------------------------------
 // A word of the lane `h` lanes to the left (h > 0) or right (h < 0), through
 // the LDS crossbar (ds_bpermute, one instruction whatever the distance).
@@ -662,14 +670,6 @@ __device__ __forceinline__ uint32_t wrap_add(uint32_t a, uint32_t b) { return a 
 __device__ __forceinline__ uint32_t wrap_sub(uint32_t a, uint32_t b) { return a - b; }
 __device__ __forceinline__ double wrap_add(double a, double b) { return a + b; }
 __device__ __forceinline__ double wrap_sub(double a, double b) { return a - b; }
-
-// Every channel of a Col at once (F(field, field of b) for each field).
-template <int M, class F> __device__ __forceinline__ void col_each(Col<M>& a, const Col<M>& b, F&& f)
-{
-    f(a.x, b.x); f(a.y, b.y); f(a.xx, b.xx); f(a.yy, b.yy);
-    if constexpr (M == MODE_F64) { f(a.xy, b.xy); f(a.miss, b.miss); }
-    else f(a.xy2, b.xy2);
-}
 
 // One step of the wavefront scan on every channel: a += a of the lane the
 // DPP control names (zero where it names none).
