@@ -596,7 +596,7 @@ def main():
         del launches
         sets = sets[:1]
         torch.cuda.empty_cache()
-        line["batched"], _ = batched_comparison(torch, swc, dev, max(10, args.steps // 4), 20)
+        line["batched"], _ = batched_comparison(torch, swc, dev, max(30, args.steps // 4), 20)
     if not args.no_schemes and args.config == "c2":
         line["window_step_sweep"] = window_step_sweep(torch, swc, sets, x.dtype, w, stream)
     if not args.no_schemes and len(w["shape"]) == 2 and tuple(w["step"]) == (1, 1):
