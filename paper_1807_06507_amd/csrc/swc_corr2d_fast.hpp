@@ -768,7 +768,8 @@ __device__ __forceinline__ void hsum_prefix(const Col<M> (&V)[R], Emit&& emit, c
 }
 
 // Window sums of one output row, whichever form fits the window width
-// (EARLY: see hsum_onehop; prow: the LDS row of the prefix form).
+// (EARLY: see hsum_onehop; it also selects the two-hop form, which single
+// launches use; prow: the LDS row of the prefix form).
 template <int M, int R, int KW, bool EARLY, class Emit>
 __device__ __forceinline__ void hsum_row(const Col<M> (&V)[R], Emit&& emit, char* prow)
 {
@@ -778,8 +779,10 @@ __device__ __forceinline__ void hsum_row(const Col<M> (&V)[R], Emit&& emit, char
         hsum_onehop<M, R, KW, EARLY>(V, emit);
     else if constexpr (fast2d_prefix(R, KW))
         hsum_prefix<M, R, KW>(V, emit, prow);
-    else if constexpr (M == MODE_F64 && hsum_two_hop<M, R, KW>())
-        hsum_twohop<M, R, KW>(V, emit);      // (the integer kernels' 168 VGPRs spill with it)
+    else if constexpr (M == MODE_F64 && EARLY && hsum_two_hop<M, R, KW>())
+        hsum_twohop<M, R, KW>(V, emit);      // (single launches of float input: the integer
+                                             // kernels' 168 VGPRs and the batch kernel's two
+                                             // rows of prefetch spill with it)
     else
         hslide<M, R, KW>(V, emit);
 }
@@ -847,8 +850,13 @@ __device__ __forceinline__ void tile2d(const P2DF& g, const int tile, char* smem
 {
     using T = typename Tr<M>::T;
     constexpr int LH = KW / 2;
-    // (one row ahead when the leaving row is read too: two loads per row in flight)
-    constexpr int D = fast2d_reread(M, R, KW, VEC) ? 1 : fast2d_depth<M, R>();
+    // Rows prefetched ahead.  When the leaving row is read too (two loads
+    // per row in flight): float input looks two rows ahead, except where the
+    // two-hop exchange holds its partial sums (single launches, k_w = 15 at
+    // R = 4), which leaves registers for one; integer input one.
+    constexpr bool kTwoHop = M == MODE_F64 && SINGLE && hsum_two_hop<M, R, KW>();
+    constexpr int D = fast2d_reread(M, R, KW, VEC) ? ((M == MODE_F64 && !kTwoHop) ? 2 : 1)
+                                                   : fast2d_depth<M, R>();
     constexpr int NW = Run<T, R>::NW;
     constexpr bool kFloat = (M == MODE_F64);
     constexpr uint32_t kFull = (1u << R) - 1u;
