@@ -283,8 +283,9 @@ typedef struct swc_batch_plan swc_batch_plan;
  * border, but must share dtype and accumulation mode, and be 2-D).  The
  * arrays x[i], y[i], c[i], flags[i] (flags may be NULL, or contain NULLs)
  * are device pointers kept by the plan.  Allocates and fills the plan's
- * device-side work list (synchronous, not capture-safe).  The plan owns that
- * memory; free it with swc_batch_plan_destroy.  `lp` may be NULL (tuned or
+ * device-side work list and two work-list counters (synchronous, not
+ * capture-safe).  The plan owns that memory; free it with
+ * swc_batch_plan_destroy.  `lp` may be NULL (tuned or
  * built-in choice); in it, tile_rows = 0 lets the plan pick about four tiles
  * per persistent wavefront, and waves_per_block = 0 (or a value whose LDS
  * rings exceed 64 KB per workgroup) the largest of 4, 2, 1 that fits. */
@@ -298,7 +299,9 @@ swc_status swc_batch_plan_create(int32_t n, const swc_problem *p, const void *co
  * group of pairs whose LDS rings allow the same number of resident
  * wavefronts per CU (at most four), plus one ordinary launch per pair without
  * a compiled window width.  Asynchronous, allocates nothing, safe to capture
- * into a hipGraph. */
+ * into a hipGraph.  The persistent waves take work items from the plan's
+ * counters, which each launch leaves at zero: launches of one plan must not
+ * overlap (issue them on one stream, or order them by events). */
 swc_status swc_batch_launch(const swc_batch_plan *plan, void *stream);
 
 /* Number of work items (tiles) in the plan, for reporting. */

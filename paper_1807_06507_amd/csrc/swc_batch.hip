@@ -4,9 +4,9 @@
 // lists of tiles: in a list, the tiles of pair i occupy [tile0_i, tile0_i + n_i).
 // The device holds one descriptor per pair (the same tile geometry the
 // single-pair register kernel uses).  One launch of a fixed, fully resident
-// grid of wavefronts walks a list: wave w takes items w, w + W, w + 2W, ...,
-// finds the pair by binary search over tile0 and runs the tile with the
-// kernel variant of that pair's window width.  A launch reserves, for every
+// grid of wavefronts walks a list: each wave takes the next item from a
+// counter in device memory, finds the pair by binary search over tile0 and
+// runs the tile with the kernel variant of that pair's window width.  A launch reserves, for every
 // wave, the LDS ring of its widest window, which caps the resident waves per
 // CU; pairs are therefore grouped by that cap (at most four groups, each one
 // persistent launch), so narrow windows are not held to the occupancy of the
@@ -49,23 +49,29 @@ template <int M>
 __global__ void __launch_bounds__(256)
 __attribute__((amdgpu_waves_per_eu(2, 8))) corr2d_batch_kernel(const BatchItem* __restrict__ items,
                                                                 int n, int64_t total,
-                                                                int64_t nwaves, int lds_stride)
+                                                                int lds_stride, int* ctr)
 {
     extern __shared__ __attribute__((aligned(16))) char smem[];
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);   // wave-uniform
-    const int wpb = blockDim.x / kWave;
-    const int64_t gid = (int64_t)xcd_remap(blockIdx.x, gridDim.x) * wpb + wv;
     char* lds = smem + (size_t)wv * lds_stride;
-    // Every wave takes the same share of the list.  Waves sharing a SIMD are
-    // issued oldest first; each wave lowers its priority as it moves through
-    // its share (3 for the first quarter down to 0 for the last), so that
-    // the waves of a SIMD keep pace and finish together.
-    const int64_t span = total - gid;
-    for (int64_t it = gid; it < total; it += nwaves) {
-        const int64_t done4 = 4 * (it - gid);
-        if (done4 < span) __builtin_amdgcn_s_setprio(3);
-        else if (done4 < 2 * span) __builtin_amdgcn_s_setprio(2);
-        else if (done4 < 3 * span) __builtin_amdgcn_s_setprio(1);
+    // Work items are handed out in list order through a counter in device
+    // memory (ctr[0]), so a wave that started late or drew cheap tiles takes
+    // more of them and the waves finish together.  Waves sharing a SIMD are
+    // issued oldest first; priorities fall from 3 to 0 as the list is used
+    // up, so that the waves of a SIMD keep pace.  The last wave to leave
+    // (ctr[1] counts them) sets both counters back to zero for the next
+    // launch, so the plan needs no clearing between launches or graph
+    // replays.
+    const int lane = threadIdx.x & (kWave - 1);
+    for (;;) {
+        int got = 0;
+        if (lane == 0) got = atomicAdd(&ctr[0], 1);
+        const int64_t it = __builtin_amdgcn_readfirstlane(got);
+        if (it >= total) break;
+        const int64_t q4 = 4 * it;
+        if (q4 < total) __builtin_amdgcn_s_setprio(3);
+        else if (q4 < 2 * total) __builtin_amdgcn_s_setprio(2);
+        else if (q4 < 3 * total) __builtin_amdgcn_s_setprio(1);
         else __builtin_amdgcn_s_setprio(0);
         // pair owning item `it` (wave-uniform)
         int lo = 0, hi = n - 1;
@@ -84,6 +90,13 @@ __attribute__((amdgpu_waves_per_eu(2, 8))) corr2d_batch_kernel(const BatchItem* 
         case 9: batch_tile<M, 9>(g, b.vec, tile, lds); break;
         case 15: batch_tile<M, 15>(g, b.vec, tile, lds); break;
         default: break;
+        }
+    }
+    if (lane == 0) {
+        const int nl = (int)(gridDim.x * (blockDim.x / kWave));
+        if (atomicAdd(&ctr[1], 1) == nl - 1) {
+            atomicExch(&ctr[0], 0);
+            atomicExch(&ctr[1], 0);
         }
     }
 }
@@ -109,6 +122,7 @@ struct swc_batch_plan {
     std::vector<BatchGroup> groups;
     int64_t total_tiles;
     BatchItem* d_items;          // device, owned (all groups' lists, concatenated)
+    int* d_ctr;                  // device, owned: next work item, waves finished
     // pairs computed by their own launches
     std::vector<swc_problem> rest_p;
     std::vector<std::array<const void*, 2>> rest_xy;
@@ -332,15 +346,28 @@ swc_status swc_batch_plan_create(int32_t n, const swc_problem* p, const void* co
         items.push_back(b);
     }
     plan->d_items = nullptr;
+    plan->d_ctr = nullptr;
+    // the work-list counters (zero at rest; each launch leaves them at zero)
+    if (hipMalloc((void**)&plan->d_ctr, 2 * sizeof(int)) != hipSuccess) {
+        delete plan;
+        return SWC_ERR_DEVICE;
+    }
+    if (hipMemset(plan->d_ctr, 0, 2 * sizeof(int)) != hipSuccess) {
+        hipFree(plan->d_ctr);
+        delete plan;
+        return SWC_ERR_DEVICE;
+    }
     plan->total_tiles = 0;
     if (!items.empty()) {
         if (hipMalloc((void**)&plan->d_items, items.size() * sizeof(BatchItem)) != hipSuccess) {
+            hipFree(plan->d_ctr);
             delete plan;
             return SWC_ERR_DEVICE;
         }
         if (hipMemcpy(plan->d_items, items.data(), items.size() * sizeof(BatchItem),
                       hipMemcpyHostToDevice) != hipSuccess) {
             hipFree(plan->d_items);
+            hipFree(plan->d_ctr);
             delete plan;
             return SWC_ERR_DEVICE;
         }
@@ -383,15 +410,15 @@ swc_status swc_batch_launch(const swc_batch_plan* plan, void* stream)
         switch (plan->mode) {
         case MODE_U8:
             e = launch_kernel(&corr2d_batch_kernel<MODE_U8>, dim3(grid), blk, smem, s, G.d_items,
-                              G.n_items, G.total_tiles, G.nwaves, G.lds_stride);
+                              G.n_items, G.total_tiles, G.lds_stride, plan->d_ctr);
             break;
         case MODE_U16:
             e = launch_kernel(&corr2d_batch_kernel<MODE_U16>, dim3(grid), blk, smem, s, G.d_items,
-                              G.n_items, G.total_tiles, G.nwaves, G.lds_stride);
+                              G.n_items, G.total_tiles, G.lds_stride, plan->d_ctr);
             break;
         default:
             e = launch_kernel(&corr2d_batch_kernel<MODE_F64>, dim3(grid), blk, smem, s, G.d_items,
-                              G.n_items, G.total_tiles, G.nwaves, G.lds_stride);
+                              G.n_items, G.total_tiles, G.lds_stride, plan->d_ctr);
             break;
         }
         if (e != hipSuccess) return sticky_error(e) ? SWC_ERR_DEVICE : SWC_ERR_LAUNCH;
@@ -415,6 +442,7 @@ void swc_batch_plan_destroy(swc_batch_plan* plan)
 {
     if (!plan) return;
     if (plan->d_items) hipFree(plan->d_items);
+    if (plan->d_ctr) hipFree(plan->d_ctr);
     delete plan;
 }
 
