@@ -4,8 +4,8 @@ variant), captured in a hipGraph and replayed.
 
 Every pair is compared with the CPU oracle (bit-exact for integer input,
 |dc| <= 2^-24 for float input); integer batches must equal single-pair
-launches bit for bit; graph replays (with eager work in between) must equal
-the eager result every time.
+launches bit for bit; graph replays (with eager work in between), repeated
+launches and alternating plans must equal the eager result every time.
 """
 import numpy as np
 import pytest
@@ -111,6 +111,32 @@ def test_batch_graph_replays():
         for c, fl, o, f in zip(outs, fls, plan.outputs, plan.flags):
             assert np.array_equal(o.cpu().numpy().view(np.uint32), c.view(np.uint32)), rep
             assert np.array_equal(f.cpu().numpy(), fl), rep
+
+
+def test_batch_relaunch_and_interleaved_plans():
+    """The persistent waves take work items from the plan's device counters,
+    which every launch leaves at zero: two plans launched alternately on one
+    stream, each several times back to back without synchronisation, must
+    give their first results every time."""
+    import torch
+    import paper_1807_06507_amd as swc
+    pa = _mixed_pairs("u16", seed=7)
+    pb = _mixed_pairs("u16", seed=8)[:5]
+    plan_a, _, outs_a, fls_a = _run_batch(pa)
+    plan_b, _, outs_b, fls_b = _run_batch(pb)
+    for rep in range(3):
+        for o in plan_a.outputs + plan_b.outputs:
+            o.fill_(7.0)
+        for _ in range(3):
+            plan_a.launch()
+            plan_b.launch()
+        torch.cuda.synchronize()
+        for outs, fls, plan in ((outs_a, fls_a, plan_a), (outs_b, fls_b, plan_b)):
+            for c, fl, o, f in zip(outs, fls, plan.outputs, plan.flags):
+                assert np.array_equal(o.cpu().numpy().view(np.uint32), c.view(np.uint32)), rep
+                assert np.array_equal(f.cpu().numpy(), fl), rep
+    for p, c, fl in zip(pa, outs_a, fls_a):
+        _check_pair(p, c, fl)
 
 
 def test_batch_config_scaled():
